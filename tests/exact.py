@@ -1,0 +1,125 @@
+"""Exact rational arithmetic used to pin the oracle (tests only).
+
+Nothing here shares code with the oracle: determinants come from the Leibniz
+permutation sum and inverses from the adjugate (Cramer's rule), both in Python
+Fractions, so they are exact and independent of any elimination order.
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+
+
+def to_frac(A) -> list[list[Fraction]]:
+    A = np.asarray(A, dtype=np.float64)
+    return [[Fraction(float(x)) for x in row] for row in A]
+
+
+def _perm_sign(p) -> int:
+    s = 1
+    p = list(p)
+    for i in range(len(p)):
+        while p[i] != i:
+            j = p[i]
+            p[i], p[j] = p[j], p[i]
+            s = -s
+    return s
+
+
+def det_leibniz(M) -> Fraction:
+    n = len(M)
+    if n == 0:
+        return Fraction(1)
+    total = Fraction(0)
+    for p in itertools.permutations(range(n)):
+        term = Fraction(_perm_sign(p))
+        for i in range(n):
+            term *= M[i][p[i]]
+            if term == 0:
+                break
+        total += term
+    return total
+
+
+def minor(M, i, j):
+    return [row[:j] + row[j + 1:] for k, row in enumerate(M) if k != i]
+
+
+def inverse_adjugate(M) -> list[list[Fraction]]:
+    """Exact inverse by adjugate / determinant (n <= 7 keeps this quick)."""
+    n = len(M)
+    d = det_leibniz(M)
+    if d == 0:
+        raise ZeroDivisionError("singular")
+    if n == 1:
+        return [[1 / M[0][0]]]
+    inv = [[Fraction(0)] * n for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            cof = det_leibniz(minor(M, i, j)) * (1 if (i + j) % 2 == 0 else -1)
+            inv[j][i] = cof / d
+    return inv
+
+
+def matmul(A, B):
+    n, q, p = len(A), len(B), len(B[0])
+    return [[sum((A[i][t] * B[t][j] for t in range(q)), Fraction(0)) for j in range(p)] for i in range(n)]
+
+
+def identity(n):
+    return [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+
+
+def sub(A, B):
+    return [[a - b for a, b in zip(ra, rb)] for ra, rb in zip(A, B)]
+
+
+def add(A, B):
+    return [[a + b for a, b in zip(ra, rb)] for ra, rb in zip(A, B)]
+
+
+def to_float(M) -> np.ndarray:
+    return np.array([[float(x) for x in row] for row in M], dtype=np.float64)
+
+
+def unit_lower_times_upper(n: int, rng, mag: int = 2):
+    """A = L U with L unit lower and U unit upper triangular small-integer
+    matrices: every leading principal minor is 1, so every leading block and
+    every Schur complement is unimodular and the exact inverse is integral."""
+    L = np.eye(n, dtype=np.int64)
+    U = np.eye(n, dtype=np.int64)
+    for i in range(n):
+        for j in range(i):
+            L[i, j] = rng.integers(-mag, mag + 1)
+            U[j, i] = rng.integers(-mag, mag + 1)
+    A = L @ U
+    # exact inverse U^-1 L^-1 by integer back substitution
+    def tri_inv_lower(T):
+        m = T.shape[0]
+        Ti = np.eye(m, dtype=object)
+        for j in range(m):
+            for i in range(j + 1, m):
+                Ti[i, j] = -sum(int(T[i, t]) * Ti[t, j] for t in range(j, i))
+        return Ti
+    Li = tri_inv_lower(L)
+    Ui = tri_inv_lower(U.T).T
+    Ai = np.dot(Ui, Li)
+    return A.astype(np.float64), np.array(Ai, dtype=np.float64), np.array(Ai, dtype=object)
+
+
+def hilbert(n: int) -> np.ndarray:
+    return np.array([[1.0 / (i + j + 1) for j in range(n)] for i in range(n)])
+
+
+def hilbert_inverse(n: int) -> np.ndarray:
+    """Closed-form integer inverse of the order-n Hilbert matrix (1-based i, j):
+    (-1)^(i+j) (i+j-1) C(n+i-1, n-j) C(n+j-1, n-i) C(i+j-2, i-1)^2."""
+    from math import comb
+    out = np.empty((n, n))
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            v = (-1) ** (i + j) * (i + j - 1) * comb(n + i - 1, n - j) * comb(n + j - 1, n - i) * comb(i + j - 2, i - 1) ** 2
+            out[i - 1, j - 1] = v
+    return out
