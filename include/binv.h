@@ -1,0 +1,127 @@
+/*
+ * binv.h -- blockwise inversion of partitioned matrices on AMD MI355X (gfx950).
+ *
+ * The library inverts a non-singular square matrix X partitioned into a k x k
+ * grid of blocks whose diagonal blocks are square (Eq. (matx) and the
+ * partitioning of §5.1: arbitrary diagonal-block orders m_i with sum m_i = n).
+ * It applies Eq. (a) of §3 -- X^-1 from A^-1 and the Schur complement
+ * S_A = D - C A^-1 B -- once per diagonal block, in place, exactly as the
+ * in-place procedure of §4.2 (invertor_inplace_by_a) does when its recursion
+ * is unrolled over the block grid.  For block p:
+ *
+ *   P      <- W_pp^-1                      pivot-block inversion (the ◊ of
+ *                                          Table 3; Gauss-Jordan with partial
+ *                                          pivoting inside the block)
+ *   W_pj   <- P W_pj,       j != p         row panel  (the -A^-1 B product)
+ *   W_ij   <- W_ij - W_ip W_pj, i,j != p   Schur complement / assembly (∼)
+ *   W_ip   <- -W_ip P,      i != p         column panel (the -C A^-1 product)
+ *   W_pp   <- P
+ *
+ * which costs 2 b_p n^2 flops per block and exactly 2 n^3 in total.  After
+ * the last block W = X^-1.  Like the paper's method, pivoting never crosses
+ * block boundaries: a block whose pivot search meets an exact zero makes the
+ * call report the matrix as singular (re-partitioning, §3, is the caller's
+ * choice).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major float64 in device memory (HBM); `ld*` is the
+ *    leading dimension in elements (>= the row length).  A column-major caller
+ *    gets the inverse of the transpose, i.e. the transpose of the inverse, and
+ *    so a correct inverse too.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it in order; the call returns once the work is enqueued unless
+ *    BINV_F_SYNC is set.
+ *  - The caller owns and frees every pointer it passes; the library keeps no
+ *    reference to them after the enqueued work completes.  Workspace belongs
+ *    to the context.  A context must not be used from two host threads at
+ *    once, nor on two streams whose work can overlap.
+ *  - Functions return a binv_status; binv_last_error() gives a thread-local
+ *    message for the last non-OK status.
+ */
+#ifndef BINV_H
+#define BINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BINV_OK = 0,
+  BINV_E_INVALID = 1,   /* bad argument (sizes, partition, pointers) */
+  BINV_E_SINGULAR = 2,  /* an exactly-zero pivot inside a diagonal block */
+  BINV_E_NOMEM = 3,     /* device allocation failed */
+  BINV_E_HIP = 5        /* a HIP runtime call failed */
+} binv_status;
+
+/* Flags for binv_opts.flags. */
+#define BINV_F_SYNC 1u    /* synchronize the stream before returning and report
+                             BINV_E_SINGULAR from the device-side info word */
+
+typedef struct {
+  int32_t k;            /* number of diagonal blocks when `part` is given */
+  const int32_t* part;  /* host array of k diagonal-block orders summing to n,
+                           or NULL to use `block` */
+  int32_t block;        /* uniform diagonal-block order when part == NULL;
+                           the last block takes the remainder; 0 = 512 */
+  uint32_t flags;       /* BINV_F_* */
+} binv_opts;
+
+typedef struct binv_ctx binv_ctx;
+
+/* Create a context on HIP device `device`.  It owns the panel workspace,
+ * which grows to the largest problem seen and is released by binv_destroy. */
+binv_status binv_create(binv_ctx** ctx, int device);
+binv_status binv_destroy(binv_ctx* ctx);
+
+/* Invert the n x n matrix A (row-major, leading dimension lda) into X
+ * (leading dimension ldx).  X == A with ldx == lda inverts in place
+ * (§4.2); otherwise A is left unchanged (§4.1's out-of-place form).
+ *
+ * d_info: optional device pointer to one int64 the call sets to 0, or to the
+ *         1-based global row of the first pivot (in block order) that was
+ *         exactly zero; X is then undefined.  With BINV_F_SYNC the status is
+ *         BINV_E_SINGULAR in that case.
+ * opts:   may be NULL (uniform blocks of 512, asynchronous).
+ * Errors: BINV_E_INVALID for n < 0, ld < n, a partition that does not sum to
+ *         n or has a non-positive order, NULL matrices with n > 0, or
+ *         overlapping A and X that are not the same matrix. */
+binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
+                        double* X, int64_t ldx, const binv_opts* opts,
+                        void* stream, int64_t* d_info);
+
+/* Per-phase kernel timing, for measurement.  Phases: */
+#define BINV_PHASE_PIVOT 0   /* pivot-block inversion (leaf kernels, sub-sweeps) */
+#define BINV_PHASE_ROW 1     /* row panel GEMM */
+#define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM */
+#define BINV_PHASE_OTHER 3   /* copies and panel saves */
+#define BINV_NPHASE 4
+
+typedef struct {
+  double ms[BINV_NPHASE];        /* summed device time of the timed launches */
+  int64_t launches[BINV_NPHASE]; /* number of timed launches */
+} binv_timing;
+
+/* Record a pair of hipEvents on the call's stream around every later launch
+ * of the phases whose bit (1 << BINV_PHASE_*) is set in `phase_mask`
+ * (0 turns timing off).  Top-level launches only: the sub-sweep of a large
+ * pivot block counts as one BINV_PHASE_PIVOT interval. */
+binv_status binv_set_timing(binv_ctx* ctx, uint32_t phase_mask);
+
+/* Wait for the recorded events, add their intervals to *out (which the caller
+ * zeroes first), and forget them. */
+binv_status binv_get_timing(binv_ctx* ctx, binv_timing* out);
+
+/* Thread-local description of the last error (never NULL). */
+const char* binv_last_error(void);
+
+/* Library version string. */
+const char* binv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BINV_H */

@@ -1,0 +1,203 @@
+"""Python binding of the blockwise inversion library (argument marshalling only).
+
+Every step of the inversion runs in the HIP kernels of ``libbinv.so``; this
+module checks tensor shapes, passes device pointers and the current HIP stream
+through ctypes, and turns status codes into exceptions.  PyTorch supplies the
+device memory and the stream.  If the library is missing the import of the
+binding fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbinv.so")
+
+BINV_OK = 0
+BINV_E_INVALID = 1
+BINV_E_SINGULAR = 2
+BINV_E_NOMEM = 3
+BINV_E_HIP = 5
+BINV_F_SYNC = 1
+
+# every exported entry point of include/binv.h
+EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
+           "binv_last_error", "binv_version")
+PHASES = ("pivot", "row", "schur", "other")
+
+
+class BinvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"binv status {status}: {msg}")
+        self.status = status
+
+
+class SingularError(BinvError):
+    pass
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32),
+        ("part", ctypes.POINTER(ctypes.c_int32)),
+        ("block", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libbinv.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it with paper_2305_11103_amd._build.build_library()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.binv_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    lib.binv_create.restype = ctypes.c_int
+    lib.binv_destroy.argtypes = [P]
+    lib.binv_destroy.restype = ctypes.c_int
+    lib.binv_invert.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
+                                ctypes.POINTER(_Opts), P, P]
+    lib.binv_invert.restype = ctypes.c_int
+    lib.binv_set_timing.argtypes = [P, ctypes.c_uint32]
+    lib.binv_set_timing.restype = ctypes.c_int
+    lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
+    lib.binv_get_timing.restype = ctypes.c_int
+    lib.binv_last_error.argtypes = []
+    lib.binv_last_error.restype = ctypes.c_char_p
+    lib.binv_version.argtypes = []
+    lib.binv_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status == BINV_OK:
+        return
+    msg = load_library().binv_last_error().decode(errors="replace")
+    if status == BINV_E_SINGULAR:
+        raise SingularError(status, msg)
+    raise BinvError(status, msg)
+
+
+class Context:
+    """A library context on one device (owns the panel workspace)."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.binv_create(ctypes.byref(h), int(device)))
+        self._h = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().binv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_timing(self, phases=()):
+        """Time every later top-level launch of the named phases with events."""
+        mask = 0
+        for p in phases:
+            mask |= 1 << PHASES.index(p)
+        _check(load_library().binv_set_timing(self._h, mask))
+
+    def get_timing(self) -> dict:
+        """Wait for the recorded events; return {phase: (total_ms, launches)}."""
+        t = _Timing()
+        _check(load_library().binv_get_timing(self._h, ctypes.byref(t)))
+        return {p: (t.ms[i], int(t.launches[i])) for i, p in enumerate(PHASES)}
+
+
+_ctx: dict[int, Context] = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]
+
+
+def _opts(part=None, block=None, sync=False):
+    o = _Opts()
+    keep = None
+    if part is not None:
+        arr = (ctypes.c_int32 * len(part))(*[int(x) for x in part])
+        keep = arr
+        o.k = len(part)
+        o.part = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    else:
+        o.k = 0
+        o.part = None
+    o.block = int(block) if block else 0
+    o.flags = BINV_F_SYNC if sync else 0
+    return o, keep
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None):
+    """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
+    inversion over the diagonal blocks `part` (or uniform blocks of `block`).
+
+    out:     optional float64 tensor for X (row stride >= n, unit column stride).
+    inplace: overwrite A with its inverse.
+    sync:    wait for completion and raise SingularError on an exactly-zero pivot.
+    info:    optional int64 CUDA tensor of one element receiving the singular row.
+    """
+    import torch
+
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"expected a square matrix, got {tuple(A.shape)}")
+    if A.dtype != torch.float64 or not A.is_cuda:
+        raise ValueError("A must be a float64 tensor on a GPU")
+    if A.stride(1) != 1:
+        raise ValueError("A must have unit column stride (row-major rows)")
+    n = A.shape[0]
+    if inplace:
+        X = A
+    elif out is not None:
+        if out.shape != A.shape or out.dtype != torch.float64 or out.stride(1) != 1 or out.device != A.device:
+            raise ValueError("out must be a float64 tensor like A")
+        X = out
+    else:
+        X = torch.empty_like(A, memory_format=torch.contiguous_format)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or default_context(dev)
+    o, keep = _opts(part, block, sync)
+    info_ptr = None
+    if info is not None:
+        if info.dtype != torch.int64 or not info.is_cuda or info.numel() < 1:
+            raise ValueError("info must be an int64 CUDA tensor with one element")
+        info_ptr = ctypes.c_void_p(info.data_ptr())
+    lda = A.stride(0) if n > 0 else 1
+    ldx = X.stride(0) if n > 0 else 1
+    with torch.cuda.device(dev):
+        st = load_library().binv_invert(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(lda, n),
+                                        ctypes.c_void_p(X.data_ptr()), max(ldx, n), ctypes.byref(o),
+                                        _stream_handle(torch, dev), info_ptr)
+    del keep
+    _check(st)
+    return X

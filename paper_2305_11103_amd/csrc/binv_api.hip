@@ -1,0 +1,323 @@
+// C ABI of the blockwise inversion library (declared in include/binv.h).
+//
+// The host side only plans and enqueues: it walks the diagonal blocks in
+// order, one elimination step per block (Eq. (a) of §3 applied in place, as
+// the in-place procedure of §4.2 does once its recursion is unrolled over the
+// block grid), and launches the kernels of kernels.hip on the caller's
+// stream.  A pivot block larger than the LDS leaf is itself inverted by the
+// same block sweep on a private copy with 64-wide sub-blocks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/binv.h"
+
+namespace binv {
+hipError_t launch_leaf_inverse(const double* A, int64_t lda, double* P, int64_t ldp, int b, int64_t row0,
+                               long long* info, hipStream_t s);
+hipError_t launch_col_save(const double* W, int64_t ldw, int64_t n, int64_t o, int b, double* Ct, int64_t ldc,
+                           hipStream_t s);
+hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
+                         hipStream_t s);
+hipError_t launch_zero_info(long long* p, hipStream_t s);
+hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
+                            double* R, int64_t ldr, hipStream_t s);
+hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
+                        int64_t o, int b, hipStream_t s);
+constexpr int kLeafMax = 128;
+constexpr int kSubBlock = 64;
+}  // namespace binv
+
+namespace {
+
+thread_local std::string g_err = "";
+
+binv_status fail(binv_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(BINV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+// A growable device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  binv_status ensure(size_t want) {
+    if (want <= bytes) return BINV_OK;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return fail(BINV_E_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    }
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      return fail(BINV_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+    return BINV_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Workspace for one recursion level of the block sweep.
+struct Level {
+  DevBuf ct;    // old column panel, k-major: b x n
+  DevBuf r;     // row panel: b x n
+  DevBuf p;     // pivot inverse: b x b
+  DevBuf sub;   // copy of a pivot block too large for the leaf kernel
+};
+
+}  // namespace
+
+struct binv_ctx {
+  int device = 0;
+  Level lv[2];
+  DevBuf info;  // scratch info word when the caller passes none
+  // optional per-phase event timing
+  uint32_t timing_mask = 0;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int phase; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+};
+
+namespace {
+
+// Brackets one top-level launch with events when its phase is being timed.
+struct PhaseTimer {
+  binv_ctx* c;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseTimer(binv_ctx* c_, int level, int phase_, hipStream_t s_) : c(c_), phase(phase_), s(s_) {
+    if (level != 0 || !(c->timing_mask & (1u << phase))) return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    if (!c->ev_free.empty()) {
+      hipEvent_t e = c->ev_free.back();
+      c->ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~PhaseTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      c->pending.push_back({phase, a, b});
+    } else {
+      if (a) c->ev_free.push_back(a);
+      if (b) c->ev_free.push_back(b);
+    }
+  }
+};
+
+binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
+                  hipStream_t s, long long* info, int64_t row0);
+
+binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw, int b, double* P, hipStream_t s,
+                         long long* info, int64_t row0) {
+  if (b <= binv::kLeafMax) {
+    HIP_TRY(binv::launch_leaf_inverse(Wpp, ldw, P, b, b, row0, info, s));
+    return BINV_OK;
+  }
+  if (level + 1 >= 2) return fail(BINV_E_INVALID, "pivot block too large for the recursion depth");
+  // invert a copy in place by the same sweep with 64-wide sub-blocks, then use it as P
+  HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
+  std::vector<int32_t> sub;
+  for (int off = 0; off < b; off += binv::kSubBlock) sub.push_back(std::min(binv::kSubBlock, b - off));
+  return sweep(c, level + 1, b, P, b, sub, s, info, row0);
+}
+
+binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
+                  hipStream_t s, long long* info, int64_t row0) {
+  int bmax = 0;
+  for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  Level& L = c->lv[level];
+  binv_status st;
+  if ((st = L.ct.ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+  if ((st = L.r.ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+  if ((st = L.p.ensure(sizeof(double) * (size_t)bmax * (size_t)bmax)) != BINV_OK) return st;
+  double* Ct = (double*)L.ct.p;
+  double* R = (double*)L.r.p;
+  double* P = (double*)L.p.p;
+  int64_t o = 0;
+  for (int32_t b : part) {
+    {
+      PhaseTimer t(c, level, BINV_PHASE_PIVOT, s);
+      if ((st = invert_pivot(c, level, W + o * ldw + o, ldw, b, P, s, info, row0 + o)) != BINV_OK) return st;
+    }
+    {
+      PhaseTimer t(c, level, BINV_PHASE_OTHER, s);
+      HIP_TRY(binv::launch_col_save(W, ldw, n, o, b, Ct, n, s));
+    }
+    {
+      PhaseTimer t(c, level, BINV_PHASE_ROW, s);
+      HIP_TRY(binv::launch_row_panel(P, b, W, ldw, n, o, b, R, n, s));
+    }
+    {
+      PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, o, b, s));
+    }
+    o += b;
+  }
+  return BINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* binv_last_error(void) { return g_err.c_str(); }
+
+const char* binv_version(void) { return "binv 0.1 (gfx950)"; }
+
+binv_status binv_create(binv_ctx** ctx, int device) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  *ctx = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(BINV_E_INVALID, "device index out of range");
+  binv_ctx* c = new (std::nothrow) binv_ctx();
+  if (!c) return fail(BINV_E_NOMEM, "out of host memory");
+  c->device = device;
+  *ctx = c;
+  return BINV_OK;
+}
+
+binv_status binv_destroy(binv_ctx* ctx) {
+  if (!ctx) return BINV_OK;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  for (auto& L : ctx->lv) {
+    L.ct.release();
+    L.r.release();
+    L.p.release();
+    L.sub.release();
+  }
+  ctx->info.release();
+  for (auto& p : ctx->pending) {
+    (void)hipEventSynchronize(p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+  (void)hipSetDevice(prev);
+  delete ctx;
+  return BINV_OK;
+}
+
+binv_status binv_set_timing(binv_ctx* ctx, uint32_t phase_mask) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  ctx->timing_mask = phase_mask & ((1u << BINV_NPHASE) - 1u);
+  return BINV_OK;
+}
+
+binv_status binv_get_timing(binv_ctx* ctx, binv_timing* out) {
+  if (!ctx || !out) return fail(BINV_E_INVALID, "NULL argument");
+  binv_status st = BINV_OK;
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+    if (e != hipSuccess && st == BINV_OK) st = fail(BINV_E_HIP, std::string("event timing: ") + hipGetErrorString(e));
+    out->ms[p.phase] += ms;
+    out->launches[p.phase] += 1;
+    ctx->ev_free.push_back(p.a);
+    ctx->ev_free.push_back(p.b);
+  }
+  ctx->pending.clear();
+  return st;
+}
+
+binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                        const binv_opts* opts, void* stream, int64_t* d_info) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (n > 0 && (!A || !X)) return fail(BINV_E_INVALID, "A or X is NULL");
+  if (n > 0 && (lda < n || ldx < n)) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  const bool inplace = (A == X);
+  if (inplace && lda != ldx) return fail(BINV_E_INVALID, "in-place call needs lda == ldx");
+  if (!inplace && n > 0) {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + (n - 1) * lda + n);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + (n - 1) * ldx + n);
+    if (a0 < x1 && x0 < a1) return fail(BINV_E_INVALID, "A and X overlap without being the same matrix");
+  }
+  std::vector<int32_t> part;
+  uint32_t flags = opts ? opts->flags : 0u;
+  if (opts && opts->part) {
+    if (opts->k <= 0) return fail(BINV_E_INVALID, "k must be positive when part is given");
+    int64_t sum = 0;
+    for (int32_t i = 0; i < opts->k; ++i) {
+      if (opts->part[i] <= 0) return fail(BINV_E_INVALID, "non-positive block order in part");
+      sum += opts->part[i];
+      part.push_back(opts->part[i]);
+    }
+    if (sum != n) return fail(BINV_E_INVALID, "block orders do not sum to n");
+  } else {
+    int32_t blk = (opts && opts->block > 0) ? opts->block : 512;
+    if (opts && opts->block < 0) return fail(BINV_E_INVALID, "negative block order");
+    for (int64_t off = 0; off < n; off += blk) part.push_back((int32_t)std::min<int64_t>(blk, n - off));
+  }
+  for (int32_t b : part)
+    if (b > binv::kLeafMax * binv::kSubBlock) return fail(BINV_E_INVALID, "diagonal block larger than 8192");
+
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  binv_status st = BINV_OK;
+  long long* info = (long long*)d_info;
+  if (!info) {
+    if ((st = ctx->info.ensure(sizeof(long long))) != BINV_OK) goto out;
+    info = (long long*)ctx->info.p;
+  }
+  {
+    hipError_t e = binv::launch_zero_info(info, s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
+  }
+  if (n > 0) {
+    if (!inplace) {
+      PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
+      hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
+    }
+    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0);
+    if (st != BINV_OK) goto out;
+  }
+  if (flags & BINV_F_SYNC) {
+    long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("sync: ") + hipGetErrorString(e)); goto out; }
+    if (h != 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
+  }
+out:
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+"""The C-ABI library loads and exports every symbol include/binv.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2305_11103_amd", "libbinv.so")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "binv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(binv_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for s in ("binv_create", "binv_destroy", "binv_invert", "binv_last_error"):
+        assert s in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_lists_every_declared_symbol():
+    from paper_2305_11103_amd import binv
+    assert sorted(binv.EXPORTS) == declared_symbols()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_version_string():
+    from paper_2305_11103_amd import binv
+    lib = binv.load_library()
+    assert lib.binv_version().decode().startswith("binv")

@@ -1,0 +1,152 @@
+"""Parity of the HIP blockwise inversion with the CPU oracle (needs a GPU).
+
+Tolerances: the gate is the normalized residual rho = ||AX - I||_F / sqrt(n)
+<= 1e-10 (measured by the oracle's compensated residual), and elementwise
+|X_gpu - X_oracle| <= 64 n u kappa max|X_oracle| with u = 2^-53.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11103_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def _inv(A_np, part=None, block=None, **kw):
+    import torch
+    from paper_2305_11103_amd import binv
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).cuda()
+    X = binv.invert(A, part=part, block=block, **kw)
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+def _check(A, X, kappa=None, rho_bound=1e-10):
+    n = A.shape[0]
+    Xo = oracle.gj_inverse(A)
+    if kappa is None:
+        kappa = np.linalg.cond(A)
+    tol = 64 * n * U * kappa * np.max(np.abs(Xo))
+    err = np.max(np.abs(X - Xo))
+    assert err <= tol, (err, tol)
+    st = oracle.residual_stats(A, X)
+    assert st["rho"] <= rho_bound, st
+    return err, st
+
+
+def test_diag_dominant_256_4x4_blocks(gpu):
+    A = wl.diag_dominant(256, wl.stream_seed(1, 0))
+    X = _inv(A, part=[64] * 4)
+    _check(A, X)
+    X2 = oracle.blockwise_inverse(A, [64] * 4)
+    assert np.max(np.abs(X - X2)) <= 64 * 256 * U * 2 * np.max(np.abs(X2))
+
+
+@pytest.mark.parametrize("n,part", [
+    (1, None), (2, [1, 1]), (5, [2, 3]), (63, [63]), (65, [64, 1]), (130, [128, 2]),
+    (300, [64, 64, 64, 64, 44]), (517, None), (1000, [200, 300, 500]), (777, [7] * 111),
+])
+def test_ragged_partitions(gpu, n, part):
+    A = wl.diag_dominant(n, 1000 + n)
+    X = _inv(A, part=part, block=128 if part is None else None)
+    _check(A, X)
+
+
+def test_spd_conditioned_1024(gpu):
+    A = wl.spd_haar(1024, 21, cond=1e4)
+    X = _inv(A, block=256)
+    _check(A, X, kappa=1e4)
+
+
+def test_inplace_equals_out_of_place_bitwise(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    A = torch.from_numpy(wl.diag_dominant(384, 5)).cuda()
+    X = binv.invert(A, block=128)
+    B = A.clone()
+    binv.invert(B, block=128, inplace=True)
+    torch.cuda.synchronize()
+    assert torch.equal(X, B)
+
+
+def test_run_to_run_bitwise(gpu):
+    A = wl.spd_haar(640, 3, cond=1e3)
+    assert np.array_equal(_inv(A, block=192), _inv(A, block=192))
+
+
+def test_padded_leading_dimension(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 200
+    A_np = wl.diag_dominant(n, 8)
+    big = torch.zeros((n, n + 13), dtype=torch.float64, device="cuda")
+    big[:, :n] = torch.from_numpy(A_np).cuda()
+    outbig = torch.full((n, n + 7), 7.0, dtype=torch.float64, device="cuda")
+    binv.invert(big[:, :n], block=64, out=outbig[:, :n])
+    torch.cuda.synchronize()
+    X = outbig[:, :n].cpu().numpy()
+    _check(A_np, X)
+    assert torch.all(outbig[:, n:] == 7.0)
+
+
+def test_block_diagonal_gives_exact_zero_off_blocks(gpu):
+    rng = np.random.default_rng(5)
+    part = [64, 100, 37, 128, 71]
+    n = sum(part)
+    M = np.zeros((n, n))
+    off = 0
+    mask = np.zeros((n, n), dtype=bool)
+    for b in part:
+        M[off:off + b, off:off + b] = rng.uniform(-1, 1, (b, b)) + b * np.eye(b)
+        mask[off:off + b, off:off + b] = True
+        off += b
+    X = _inv(M, part=part)
+    assert np.all(X[~mask] == 0.0)
+    _check(M, X)
+
+
+def test_unit_bidiagonal_exact(gpu):
+    n = 300
+    L = np.eye(n) - np.eye(n, k=-1)
+    X = _inv(L, part=[64, 64, 100, 72])
+    assert np.array_equal(X, np.tril(np.ones((n, n))))
+
+
+def test_reversal_permutation_is_singular(gpu):
+    from paper_2305_11103_amd import binv
+    n = 128
+    J = np.eye(n)[::-1].copy()
+    with pytest.raises(binv.SingularError):
+        _inv(J, part=[64, 64])
+
+
+def test_singular_row_reported(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 96
+    A = wl.diag_dominant(n, 2)
+    A[:, 40] = 0.0  # column 40 stays zero through step 0, so block 1 meets a zero pivot there
+    info = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(binv.SingularError):
+        binv.invert(torch.from_numpy(A).cuda(), part=[32, 32, 32], info=info)
+    assert int(info.item()) == 41
+    with pytest.raises(oracle.SingularError) as e:
+        oracle.gj_inverse(A)
+    assert e.value.row == 41
+
+
+def test_empty_matrix(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    X = binv.invert(torch.zeros((0, 0), dtype=torch.float64, device="cuda"))
+    assert X.shape == (0, 0)
+
+
+def test_invalid_partition_rejected(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    A = torch.eye(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(binv.BinvError):
+        binv.invert(A, part=[3, 3])

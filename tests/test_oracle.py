@@ -257,6 +257,9 @@ def test_partial_sweep_exact_on_unit_lu():
     Y = [[Fraction(float(x)) for x in row[4:]] for row in W[:4]]
     assert exact.matmul(A11, Y) == [r[4:] for r in Af[:4]]
     assert exact.to_float(A11i).tolist() == W[:4, :4].tolist()
+    # the column panel Z satisfies Z A11 = -A21 exactly
+    Z = [[Fraction(float(x)) for x in row[:4]] for row in W[4:]]
+    assert exact.matmul(Z, A11) == [[-x for x in r[:4]] for r in Af[4:]]
 
 
 # --------------------------------------------------------------------------
