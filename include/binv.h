@@ -59,6 +59,15 @@ typedef enum {
 /* Flags for binv_opts.flags. */
 #define BINV_F_SYNC 1u    /* synchronize the stream before returning and report
                              BINV_E_SINGULAR from the device-side info word */
+#define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only.
+                             By default, block p+1's row/column band is updated
+                             first, then block p+1's pivot block is inverted
+                             on an internal stream restricted to a few CUs
+                             while the rest of block p's trailing update runs
+                             on another internal stream restricted to the
+                             other CUs; both join back to the caller's stream
+                             before the call's work ends.  Results are bitwise
+                             identical either way. */
 
 typedef struct {
   int32_t k;            /* number of diagonal blocks when `part` is given */
@@ -95,19 +104,24 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
 /* Per-phase kernel timing, for measurement.  Phases: */
 #define BINV_PHASE_PIVOT 0   /* pivot-block inversion (leaf kernels, sub-sweeps) */
 #define BINV_PHASE_ROW 1     /* row panel GEMM */
-#define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM */
+#define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM (all tiles, or all
+                                but the next block's band under lookahead) */
 #define BINV_PHASE_OTHER 3   /* copies and panel saves */
-#define BINV_NPHASE 4
+#define BINV_PHASE_BAND 4    /* lookahead: Schur update of the next block's
+                                row and column band, on the side stream */
+#define BINV_NPHASE 5
 
 typedef struct {
   double ms[BINV_NPHASE];        /* summed device time of the timed launches */
   int64_t launches[BINV_NPHASE]; /* number of timed launches */
+  double flops[BINV_NPHASE];     /* summed algorithmic flops of those launches
+                                    (2 K per output element contracted) */
 } binv_timing;
 
-/* Record a pair of hipEvents on the call's stream around every later launch
- * of the phases whose bit (1 << BINV_PHASE_*) is set in `phase_mask`
- * (0 turns timing off).  Top-level launches only: the sub-sweep of a large
- * pivot block counts as one BINV_PHASE_PIVOT interval. */
+/* Record a pair of hipEvents around every later launch of the phases whose
+ * bit (1 << BINV_PHASE_*) is set in `phase_mask` (0 turns timing off), on the
+ * stream that launch runs on.  Top-level launches only: the sub-sweep of a
+ * large pivot block counts as one BINV_PHASE_PIVOT interval. */
 binv_status binv_set_timing(binv_ctx* ctx, uint32_t phase_mask);
 
 /* Wait for the recorded events, add their intervals to *out (which the caller

@@ -20,11 +20,12 @@ BINV_E_SINGULAR = 2
 BINV_E_NOMEM = 3
 BINV_E_HIP = 5
 BINV_F_SYNC = 1
+BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
            "binv_last_error", "binv_version")
-PHASES = ("pivot", "row", "schur", "other")
+PHASES = ("pivot", "row", "schur", "other", "band")
 
 
 class BinvError(RuntimeError):
@@ -38,7 +39,7 @@ class SingularError(BinvError):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5), ("flops", ctypes.c_double * 5)]
 
 
 class _Opts(ctypes.Structure):
@@ -123,10 +124,10 @@ class Context:
         _check(load_library().binv_set_timing(self._h, mask))
 
     def get_timing(self) -> dict:
-        """Wait for the recorded events; return {phase: (total_ms, launches)}."""
+        """Wait for the recorded events; return {phase: (total_ms, launches, flops)}."""
         t = _Timing()
         _check(load_library().binv_get_timing(self._h, ctypes.byref(t)))
-        return {p: (t.ms[i], int(t.launches[i])) for i, p in enumerate(PHASES)}
+        return {p: (t.ms[i], int(t.launches[i]), t.flops[i]) for i, p in enumerate(PHASES)}
 
 
 _ctx: dict[int, Context] = {}
@@ -138,7 +139,7 @@ def default_context(device: int = 0) -> Context:
     return _ctx[device]
 
 
-def _opts(part=None, block=None, sync=False):
+def _opts(part=None, block=None, sync=False, lookahead=True):
     o = _Opts()
     keep = None
     if part is not None:
@@ -150,7 +151,7 @@ def _opts(part=None, block=None, sync=False):
         o.k = 0
         o.part = None
     o.block = int(block) if block else 0
-    o.flags = BINV_F_SYNC if sync else 0
+    o.flags = (BINV_F_SYNC if sync else 0) | (0 if lookahead else BINV_F_NO_LOOKAHEAD)
     return o, keep
 
 
@@ -158,13 +159,15 @@ def _stream_handle(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None):
+def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True):
     """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
     inversion over the diagonal blocks `part` (or uniform blocks of `block`).
 
     out:     optional float64 tensor for X (row stride >= n, unit column stride).
     inplace: overwrite A with its inverse.
     sync:    wait for completion and raise SingularError on an exactly-zero pivot.
+    lookahead: form the next block's pivot and panels on a side stream while
+             the current trailing update runs (bitwise identical results).
     info:    optional int64 CUDA tensor of one element receiving the singular row.
     """
     import torch
@@ -186,7 +189,7 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
         X = torch.empty_like(A, memory_format=torch.contiguous_format)
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
     ctx = ctx or default_context(dev)
-    o, keep = _opts(part, block, sync)
+    o, keep = _opts(part, block, sync, lookahead)
     info_ptr = None
     if info is not None:
         if info.dtype != torch.int64 or not info.is_cuda or info.numel() < 1:

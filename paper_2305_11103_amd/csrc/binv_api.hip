@@ -27,9 +27,9 @@ hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, i
                          hipStream_t s);
 hipError_t launch_zero_info(long long* p, hipStream_t s);
 hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
-                            double* R, int64_t ldr, hipStream_t s);
+                            double* R, int64_t ldr, hipStream_t s, double* flops);
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
-                        int64_t o, int b, hipStream_t s);
+                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
 constexpr int kLeafMax = 128;
 constexpr int kSubBlock = 64;
 }  // namespace binv
@@ -76,24 +76,30 @@ struct DevBuf {
   }
 };
 
-// Workspace for one recursion level of the block sweep.
+// Workspace for one recursion level of the block sweep (two sets of panels:
+// under lookahead the next block's panels are formed while the current ones
+// are still being read).
 struct Level {
-  DevBuf ct;    // old column panel, k-major: b x n
-  DevBuf r;     // row panel: b x n
-  DevBuf p;     // pivot inverse: b x b
-  DevBuf sub;   // copy of a pivot block too large for the leaf kernel
+  DevBuf ct[2];  // old column panel, k-major: b x n
+  DevBuf r[2];   // row panel: b x n
+  DevBuf p[2];   // pivot inverse: b x b
 };
 
 }  // namespace
 
 struct binv_ctx {
   int device = 0;
+  int ncu = 256;  // compute units of the device
   Level lv[2];
   DevBuf info;  // scratch info word when the caller passes none
+  // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few
+  // CUs) while the next pivot inversion runs on `side` (masked to the rest)
+  hipStream_t side = nullptr, gemm = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
   // optional per-phase event timing
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t> ev_free;
-  struct Pending { int phase; hipEvent_t a, b; };
+  struct Pending { int phase; hipEvent_t a, b; double flops; };
   std::vector<Pending> pending;
 };
 
@@ -105,6 +111,9 @@ struct PhaseTimer {
   int phase;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
+  double flops = 0.0;
+  bool on() const { return a && b; }
+  double* fl() { return on() ? &flops : nullptr; }
   PhaseTimer(binv_ctx* c_, int level, int phase_, hipStream_t s_) : c(c_), phase(phase_), s(s_) {
     if (level != 0 || !(c->timing_mask & (1u << phase))) return;
     a = take();
@@ -124,7 +133,7 @@ struct PhaseTimer {
   ~PhaseTimer() {
     if (a && b) {
       (void)hipEventRecord(b, s);
-      c->pending.push_back({phase, a, b});
+      c->pending.push_back({phase, a, b, flops});
     } else {
       if (a) c->ev_free.push_back(a);
       if (b) c->ev_free.push_back(b);
@@ -133,7 +142,7 @@ struct PhaseTimer {
 };
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
-                  hipStream_t s, long long* info, int64_t row0);
+                  hipStream_t s, long long* info, int64_t row0, bool lookahead);
 
 binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw, int b, double* P, hipStream_t s,
                          long long* info, int64_t row0) {
@@ -146,40 +155,122 @@ binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw,
   HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
   std::vector<int32_t> sub;
   for (int off = 0; off < b; off += binv::kSubBlock) sub.push_back(std::min(binv::kSubBlock, b - off));
-  return sweep(c, level + 1, b, P, b, sub, s, info, row0);
+  return sweep(c, level + 1, b, P, b, sub, s, info, row0, false);
+}
+
+// Pivot inversion of block [o, o+b) into panel set `buf`, on stream s.
+binv_status block_pivot(binv_ctx* c, int level, double* W, int64_t ldw, int64_t o, int b, int buf, hipStream_t s,
+                        long long* info, int64_t row0) {
+  PhaseTimer t(c, level, BINV_PHASE_PIVOT, s);
+  return invert_pivot(c, level, W + o * ldw + o, ldw, b, (double*)c->lv[level].p[buf].p, s, info, row0 + o);
+}
+
+// Column-panel save and row panel of block [o, o+b) into panel set `buf`.
+binv_status block_panels(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, int64_t o, int b, int buf,
+                         hipStream_t s) {
+  Level& L = c->lv[level];
+  {
+    PhaseTimer t(c, level, BINV_PHASE_OTHER, s);
+    HIP_TRY(binv::launch_col_save(W, ldw, n, o, b, (double*)L.ct[buf].p, n, s));
+  }
+  {
+    PhaseTimer t(c, level, BINV_PHASE_ROW, s);
+    HIP_TRY(binv::launch_row_panel((double*)L.p[buf].p, b, W, ldw, n, o, b, (double*)L.r[buf].p, n, s, t.fl()));
+  }
+  return BINV_OK;
+}
+
+// CUs given to the pivot sub-sweep while the trailing update runs.
+constexpr int kReserveCUs = 8;
+
+binv_status ensure_side(binv_ctx* c) {
+  if (c->side) return BINV_OK;
+  const int words = (c->ncu + 31) / 32;
+  std::vector<uint32_t> mg(words, 0u), ms(words, 0u);
+  for (int cu = 0; cu < c->ncu; ++cu) {
+    if (cu < c->ncu - kReserveCUs) mg[cu / 32] |= 1u << (cu % 32);
+    else ms[cu / 32] |= 1u << (cu % 32);
+  }
+  // CU-masked streams; plain streams if masking is unavailable
+  if (c->ncu <= 2 * kReserveCUs ||
+      hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) != hipSuccess ||
+      hipExtStreamCreateWithCUMask(&c->side, (uint32_t)words, ms.data()) != hipSuccess) {
+    if (c->gemm) (void)hipStreamDestroy(c->gemm);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->gemm = c->side = nullptr;
+    (void)hipGetLastError();
+    HIP_TRY(hipStreamCreateWithFlags(&c->gemm, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_gemm, hipEventDisableTiming));
+  return BINV_OK;
 }
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
-                  hipStream_t s, long long* info, int64_t row0) {
+                  hipStream_t s, long long* info, int64_t row0, bool lookahead) {
   int bmax = 0;
   for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  const int k = (int)part.size();
+  lookahead = lookahead && level == 0 && k >= 2;
   Level& L = c->lv[level];
   binv_status st;
-  if ((st = L.ct.ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
-  if ((st = L.r.ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
-  if ((st = L.p.ensure(sizeof(double) * (size_t)bmax * (size_t)bmax)) != BINV_OK) return st;
-  double* Ct = (double*)L.ct.p;
-  double* R = (double*)L.r.p;
-  double* P = (double*)L.p.p;
-  int64_t o = 0;
-  for (int32_t b : part) {
-    {
-      PhaseTimer t(c, level, BINV_PHASE_PIVOT, s);
-      if ((st = invert_pivot(c, level, W + o * ldw + o, ldw, b, P, s, info, row0 + o)) != BINV_OK) return st;
-    }
-    {
-      PhaseTimer t(c, level, BINV_PHASE_OTHER, s);
-      HIP_TRY(binv::launch_col_save(W, ldw, n, o, b, Ct, n, s));
-    }
-    {
-      PhaseTimer t(c, level, BINV_PHASE_ROW, s);
-      HIP_TRY(binv::launch_row_panel(P, b, W, ldw, n, o, b, R, n, s));
-    }
-    {
+  for (int h = 0; h < (lookahead ? 2 : 1); ++h) {
+    if ((st = L.ct[h].ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+    if ((st = L.r[h].ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+    if ((st = L.p[h].ensure(sizeof(double) * (size_t)bmax * (size_t)bmax)) != BINV_OK) return st;
+  }
+  if (lookahead && (st = ensure_side(c)) != BINV_OK) return st;
+  std::vector<int64_t> off(k + 1, 0);
+  for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
+
+  if (!lookahead) {
+    for (int p = 0; p < k; ++p) {
+      if ((st = block_pivot(c, level, W, ldw, off[p], part[p], 0, s, info, row0)) != BINV_OK) return st;
+      if ((st = block_panels(c, level, n, W, ldw, off[p], part[p], 0, s)) != BINV_OK) return st;
       PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
-      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, o, b, s));
+      HIP_TRY(binv::launch_schur((double*)L.ct[0].p, n, (double*)L.r[0].p, n, W, ldw, n, off[p], part[p], 0, 0, 0, s,
+                                 t.fl(), 0));
     }
-    o += b;
+    return BINV_OK;
+  }
+
+  // Lookahead.  Step p: update block q = p+1's row/column band first (whole
+  // device), then invert q's pivot block on the side stream (a few reserved
+  // CUs) while the rest of step p's trailing update runs on the other CUs;
+  // join, and form q's column and row panels.  The pivot chain is thus off the
+  // critical path whenever it is shorter than the trailing update.
+  if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) return st;
+  if ((st = block_panels(c, level, n, W, ldw, off[0], part[0], 0, s)) != BINV_OK) return st;
+  for (int p = 0; p < k; ++p) {
+    const int cur = p & 1;
+    const double* Ct = (const double*)L.ct[cur].p;
+    const double* R = (const double*)L.r[cur].p;
+    if (p + 1 < k) {
+      {
+        PhaseTimer t(c, level, BINV_PHASE_BAND, s);
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 1, off[p + 1], part[p + 1], s, t.fl(), 0));
+      }
+      HIP_TRY(hipEventRecord(c->ev_fork, s));
+      HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      HIP_TRY(hipStreamWaitEvent(c->gemm, c->ev_fork, 0));
+      if ((st = block_pivot(c, level, W, ldw, off[p + 1], part[p + 1], cur ^ 1, c->side, info, row0)) != BINV_OK)
+        return st;
+      HIP_TRY(hipEventRecord(c->ev_join, c->side));
+      {
+        PhaseTimer t(c, level, BINV_PHASE_SCHUR, c->gemm);
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 2, off[p + 1], part[p + 1], c->gemm,
+                                   t.fl(), 0));
+      }
+      HIP_TRY(hipEventRecord(c->ev_gemm, c->gemm));
+      HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));
+      HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+      if ((st = block_panels(c, level, n, W, ldw, off[p + 1], part[p + 1], cur ^ 1, s)) != BINV_OK) return st;
+    } else {
+      PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, s, t.fl(), 0));
+    }
   }
   return BINV_OK;
 }
@@ -201,6 +292,9 @@ binv_status binv_create(binv_ctx** ctx, int device) {
   binv_ctx* c = new (std::nothrow) binv_ctx();
   if (!c) return fail(BINV_E_NOMEM, "out of host memory");
   c->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->ncu = ncu;
   *ctx = c;
   return BINV_OK;
 }
@@ -210,12 +304,19 @@ binv_status binv_destroy(binv_ctx* ctx) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(ctx->device);
-  for (auto& L : ctx->lv) {
-    L.ct.release();
-    L.r.release();
-    L.p.release();
-    L.sub.release();
-  }
+  for (auto& L : ctx->lv)
+    for (int h = 0; h < 2; ++h) {
+      L.ct[h].release();
+      L.r[h].release();
+      L.p[h].release();
+    }
+  for (hipStream_t st : {ctx->side, ctx->gemm})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_gemm})
+    if (e) (void)hipEventDestroy(e);
   ctx->info.release();
   for (auto& p : ctx->pending) {
     (void)hipEventSynchronize(p.b);
@@ -244,6 +345,7 @@ binv_status binv_get_timing(binv_ctx* ctx, binv_timing* out) {
     if (e != hipSuccess && st == BINV_OK) st = fail(BINV_E_HIP, std::string("event timing: ") + hipGetErrorString(e));
     out->ms[p.phase] += ms;
     out->launches[p.phase] += 1;
+    out->flops[p.phase] += p.flops;
     ctx->ev_free.push_back(p.a);
     ctx->ev_free.push_back(p.b);
   }
@@ -305,7 +407,7 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
     }
-    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0);
+    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, !(flags & BINV_F_NO_LOOKAHEAD));
     if (st != BINV_OK) goto out;
   }
   if (flags & BINV_F_SYNC) {

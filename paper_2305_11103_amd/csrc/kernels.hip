@@ -5,7 +5,7 @@
 // of §3 applied in place as in §4.2:
 //
 //   k_leaf_inverse   P = W_pp^-1 by Gauss-Jordan with partial pivoting inside
-//                    the block, held entirely in LDS (b <= 128).
+//                    the block, held in registers (b <= 128).
 //   k_col_save       Ct = (W[:, o:o+b])^T, the old column panel, k-major.
 //   k_gemm_step<ROW> R = P W[o:o+b, :] with R[:, o:o+b] = P  (row panel,
 //                    "-A^-1 B" up to sign; the p columns carry P itself).
@@ -32,103 +32,158 @@ constexpr int kNT = 256;        // threads per workgroup in the GEMM and leaf ke
 constexpr int kLeafMax = 128;   // largest pivot block the LDS leaf kernel holds
 
 // ---------------------------------------------------------------------------
-// Leaf: Gauss-Jordan with partial pivoting on a b x b block in LDS.
+// Leaf: Gauss-Jordan with partial pivoting on a b x b block held in registers.
 // ---------------------------------------------------------------------------
-// A (lda): the block, read only.  P (ldp): receives the inverse.
-// info: set (first writer wins) to row0 + c + 1 when the pivot of column c is
-// exactly zero; the block's output is then undefined.
-template <int BMAX>
-__global__ void __launch_bounds__(kNT) k_leaf_inverse(const double* __restrict__ A, int64_t lda,
-                                                      double* __restrict__ P, int64_t ldp, int b,
-                                                      int64_t row0, long long* info) {
-  constexpr int LD = BMAX + 1;
-  __shared__ double W[BMAX * LD];
-  __shared__ double fcol[BMAX];
-  __shared__ int perm[BMAX];
-  __shared__ int colmap[BMAX];
-  __shared__ int s_piv;
-  __shared__ double s_pval;
+// Layout: NWV waves; wave w owns columns [w*CPW, (w+1)*CPW); lane l owns
+// rows l + 64 h (h < RPL).  Column c is eliminated in one pass:
+//   - the owning wave finds the pivot (largest |value| among rows not yet used
+//     as pivots, lowest row on ties), publishes it and the column of
+//     multipliers through LDS (double-buffered, so one barrier per column);
+//   - in every wave the pivot row is broadcast with readlane; every other row
+//     does w_ij -= (f_i q) p_j with q = 1/pivot, the pivot row is scaled by q;
+//     the column-c slot of the other rows becomes -f_i q and that of the
+//     pivot row q.
+// Rows are not physically swapped: row r_c used for column c stays where it
+// is.  This is Gauss-Jordan on the row-permuted matrix B (B[c] = A[r_c]), so
+// the stored result satisfies A^-1[c][r_m] = W[r_c][m], which the final store
+// applies.
+// A (lda): the block, read only.  P (ldp): receives the inverse.  info: set
+// (first writer wins) to row0 + c + 1 when the pivot of column c is exactly
+// zero; P is then undefined.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int RPL, int CPW, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restrict__ A, int64_t lda,
+                                                           double* __restrict__ P, int64_t ldp, int b,
+                                                           int64_t row0, long long* info) {
+  constexpr int NB = NWV * CPW;  // the block is padded to NB x NB with an identity
+  static_assert(NB <= 64 * RPL, "columns exceed rows");
+  __shared__ double colbuf[2][64 * RPL];
+  __shared__ int s_r[2];
+  __shared__ double s_pv[2];
+  __shared__ int piv_row[NB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  constexpr int NW = kNT / 64;
+  const int cbase = wave * CPW;
 
-  for (int e = tid; e < b * b; e += kNT) {
-    int i = e / b, j = e - i * b;
-    W[i * LD + j] = A[(int64_t)i * lda + j];
+  // diag(A, I) has inverse diag(A^-1, I): padding keeps the loop uniform.
+  double v[RPL][CPW];
+  bool used[RPL];
+  int step_of[RPL];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int row = lane + 64 * h;
+    used[h] = row >= NB;  // rows beyond the padded block never pivot
+    step_of[h] = 0;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = cbase + j;
+      v[h][j] = (row < b && col < b) ? A[(int64_t)row * lda + col] : (row == col ? 1.0 : 0.0);
+    }
   }
-  __syncthreads();
 
   bool singular = false;
-  for (int c = 0; c < b; ++c) {
-    // pivot search on column c, rows c..b-1: wave 0, lowest row wins ties
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = BMAX;
-      for (int i = c + lane; i < b; i += 64) {
-        double v = fabs(W[i * LD + c]);
-        if (v > best) { best = v; bi = i; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(best, off, 64);
-        int oi = __shfl_xor(bi, off, 64);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (lane == 0) {
-        s_piv = bi;
-        s_pval = W[bi * LD + c];
-        perm[c] = bi;
-      }
-    }
-    __syncthreads();
-    const int r = s_piv;
-    const double pv = s_pval;
-    if (pv == 0.0) {
-      if (tid == 0) atomicCAS((unsigned long long*)info, 0ULL, (unsigned long long)(row0 + c + 1));
-      singular = true;
-      break;
-    }
-    if (r != c) {
-      for (int j = tid; j < b; j += kNT) {
-        double t = W[c * LD + j];
-        W[c * LD + j] = W[r * LD + j];
-        W[r * LD + j] = t;
+  for (int cw = 0; cw < NWV; ++cw) {
+    const bool owner = (wave == cw);
+#pragma unroll
+    for (int t = 0; t < CPW; ++t) {
+      const int c = cw * CPW + t;
+      const int buf = c & 1;
+      if (owner) {
+        // Pivot search.  For non-negative doubles the IEEE bit pattern orders
+        // like the value, so key = bits(|v|) + 1 (0 for rows already used)
+        // turns the search into one integer wave-max; ties go to the lowest row.
+        unsigned long long key[RPL];
+        unsigned long long kmax = 0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          key[h] = used[h] ? 0ULL : (unsigned long long)__double_as_longlong(fabs(v[h][t])) + 1ULL;
+          kmax = key[h] > kmax ? key[h] : kmax;
+        }
+        {
+          // 64-bit wave max as two 32-bit DPP reductions (high word, then low)
+          const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
+          const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
+          kmax = ((unsigned long long)hi << 32) | lo;
+        }
+        int r = 64 * RPL;
+#pragma unroll
+        for (int h = RPL - 1; h >= 0; --h) {
+          const unsigned long long mk = __ballot(key[h] == kmax);
+          if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
+        }
+        double pv = 0.0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          colbuf[buf][lane + 64 * h] = v[h][t];
+          if ((r >> 6) == h) pv = readlane_f64(v[h][t], r & 63);
+        }
+        if (lane == 0) {
+          s_r[buf] = r;
+          s_pv[buf] = pv;
+        }
       }
       __syncthreads();
-    }
-    const double q = 1.0 / pv;
-    // save column c (multipliers) and scale the pivot row; its column-c slot becomes q
-    for (int i = tid; i < b; i += kNT) fcol[i] = (i == c) ? 0.0 : W[i * LD + c];
-    for (int j = tid; j < b; j += kNT) W[c * LD + j] = (j == c ? 1.0 : W[c * LD + j]) * q;
-    __syncthreads();
-    // eliminate column c from every other row; column c receives -f q
-    for (int i = wave; i < b; i += NW) {
-      if (i == c) continue;
-      const double f = fcol[i];
-      for (int j = lane; j < b; j += 64) {
-        double w = (j == c) ? 0.0 : W[i * LD + j];
-        W[i * LD + j] = w - f * W[c * LD + j];
+      const int r = s_r[buf];
+      const double pv = s_pv[buf];
+      if (pv == 0.0 && !singular) {
+        // exactly-zero pivot: record it; the arithmetic runs on (inf/nan) and
+        // the result is not stored
+        if (tid == 0) atomicCAS((unsigned long long*)info, 0ULL, (unsigned long long)(row0 + c + 1));
+        singular = true;
       }
+      const double q = 1.0 / pv;
+      // uniform: keep the pivot lane and row half in scalar registers
+      const int rl = __builtin_amdgcn_readfirstlane(r & 63);
+      const int rh = (RPL == 1) ? 0 : __builtin_amdgcn_readfirstlane(r >> 6);
+      // Broadcast the unscaled pivot row p (readlane), with p_c taken as 1.
+      // Row i != r becomes w_ij - (f_i q) p_j: the column-c slot, zeroed
+      // first, ends as -f_i q.  The pivot row uses f = 0 and is multiplied by
+      // q (its column-c slot set to 1 first, so it ends as q).
+      double sp[CPW];
+      if (RPL == 1 || rh == 0) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[0][j], rl);
+      } else {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[RPL - 1][j], rl);
+      }
+      sp[t] = owner ? 1.0 : sp[t];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        const int row = lane + 64 * h;
+        const bool isr = (row == r);
+        const double fq = isr ? 0.0 : colbuf[buf][row] * q;
+        const double a = isr ? q : 1.0;
+        v[h][t] = owner ? (isr ? 1.0 : 0.0) : v[h][t];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) v[h][j] = fma(-fq, sp[j], v[h][j]) * a;
+        used[h] = used[h] || isr;
+        step_of[h] = isr ? c : step_of[h];
+      }
+      if (tid == 0) piv_row[c] = r;
     }
-    __syncthreads();
   }
   if (singular) return;
-  // undo the row interchanges as column interchanges in reverse order:
-  // final[:, j] = W[:, colmap[j]]
-  if (tid == 0) {
-    for (int j = 0; j < b; ++j) colmap[j] = j;
-    for (int c = b - 1; c >= 0; --c) {
-      int r = perm[c];
-      int t = colmap[c];
-      colmap[c] = colmap[r];
-      colmap[r] = t;
-    }
-  }
   __syncthreads();
-  for (int e = tid; e < b * b; e += kNT) {
-    int i = e / b, j = e - i * b;
-    P[(int64_t)i * ldp + j] = W[i * LD + colmap[j]];
+  // A^-1[step_of(row)][piv_row[col]] = W[row][col]
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int row = lane + 64 * h;
+    if (row >= b) continue;
+    double* dst = P + (int64_t)step_of[h] * ldp;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = cbase + j;
+      if (col < b) dst[piv_row[col]] = v[h][j];
+    }
   }
 }
 
@@ -192,89 +247,180 @@ struct StepArgs {
   int K;             // contraction length (= b)
   int64_t o;         // first row/column of block p
   int b;             // order of block p
+  // tile subset (MODE_SCHUR): 0 = every tile; 1 = the band of tile-rows
+  // [tr0, tr1] and tile-columns [tc0, tc1] (the next block's rows and
+  // columns); 2 = every tile outside that band.
+  int region;
+  int64_t tr0, tr1, tc0, tc1;
+  int64_t ntiles;    // tiles enumerated by the region (before band skipping)
 };
 
-template <int MODE, int BM, int BN, bool A_KMAJOR>
-__global__ void __launch_bounds__(kNT, (BM * BN >= 128 * 128) ? 1 : 2) k_gemm_step(StepArgs g) {
+// Tile order: the grid is 1-D and persistent.  Workgroups are dealt to the 8
+// XCDs round-robin (workgroup g runs on XCD g % 8), so XCD x owns the
+// contiguous tile range [x T8, (x+1) T8) and its workgroups stride through it.
+// Inside the range tiles go in groups of GM tile-rows (column-major inside a
+// group), so the workgroups resident on one XCD share row and column panels in
+// that XCD's L2.  Region 1 enumerates only the band of tile-rows [tr0, tr1]
+// and tile-columns [tc0, tc1]; region 2 skips that band.
+template <int GM>
+__device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64_t& tm, int64_t& tn, int region,
+                                        int64_t tr0, int64_t tr1, int64_t tc0, int64_t tc1) {
+  if (region == 1) {
+    const int64_t nr = tr1 - tr0 + 1, nc = tc1 - tc0 + 1;
+    const int64_t T1 = nr * TN;
+    if (t < T1) {
+      tm = tr0 + t / TN;
+      tn = t % TN;
+      return true;
+    }
+    const int64_t u = t - T1;
+    if (u >= (TM - nr) * nc) return false;
+    tn = tc0 + u % nc;
+    const int64_t mi = u / nc;
+    tm = (mi < tr0) ? mi : mi + nr;
+    return true;
+  }
+  if (t >= TM * TN) return false;
+  const int64_t per_group = (int64_t)GM * TN;
+  const int64_t group = t / per_group;
+  const int64_t first = group * GM;
+  const int64_t rows = (TM - first < GM) ? (TM - first) : GM;
+  const int64_t r = t - group * per_group;
+  tm = first + r % rows;
+  tn = r / rows;
+  if (region == 2 && ((tm >= tr0 && tm <= tr1) || (tn >= tc0 && tn <= tc1))) return false;
+  return true;
+}
+
+// VEC: every tile is interior, K is a multiple of BK and rows are 16-byte
+// aligned, so global loads are unguarded double2 loads; otherwise loads are
+// guarded element by element.
+template <int MODE, int BM, int BN, bool A_KMAJOR, bool VEC>
+__global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
   constexpr int BK = 16;
   constexpr int PAD = 4;
   constexpr int LA = BM + PAD;
   constexpr int LB = BN + PAD;
   constexpr int WM = BM / 2, WN = BN / 2;   // 2 x 2 waves
   constexpr int RG = WM / 4, CG = WN / 16;  // 4x16 MFMA tiles per wave
-  constexpr int A_ELEMS = BK * BM / kNT;    // per-thread global loads per chunk
-  constexpr int B_ELEMS = BK * BN / kNT;
+  constexpr int A_V2 = BK * BM / 2 / kNT;   // per-thread double2 loads per chunk
+  constexpr int B_V2 = BK * BN / 2 / kNT;
+  static_assert(A_V2 * 2 * kNT == BK * BM && B_V2 * 2 * kNT == BK * BN, "tile/thread mismatch");
   __shared__ double As[2][BK * LA];
   __shared__ double Bs[2][BK * LB];
+
+  const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+  const int64_t T8 = (g.ntiles + 7) / 8;
+  const int64_t xcd = blockIdx.x & 7, per = (int64_t)gridDim.x >> 3;
+  for (int64_t tl = (int64_t)blockIdx.x >> 3; tl < T8; tl += per) {
+  int64_t tm, tn;
+  if (!tile_of<8>(xcd * T8 + tl, TM, TN, tm, tn, g.region, g.tr0, g.tr1, g.tc0, g.tc1)) continue;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  const int64_t m0 = tm * BM;
+  const int64_t n0 = tn * BN;
   const int64_t o = g.o;
   const int b = g.b;
 
   // Does this tile need the contraction at all?
   bool need = true;
   if (MODE == MODE_SCHUR) {
-    // rows entirely inside block p are a pure copy of R
-    if (m0 >= o && m0 + BM <= o + b) need = false;
+    if (m0 >= o && m0 + BM <= o + b) need = false;  // rows inside block p: copy of R
   } else {
-    // columns entirely inside block p are a copy of P
-    if (n0 >= o && n0 + BN <= o + b) need = false;
+    if (n0 >= o && n0 + BN <= o + b) need = false;  // columns inside block p: copy of P
   }
 
-  dbl acc[RG][CG];
+  double acc[RG][CG];
 #pragma unroll
   for (int r = 0; r < RG; ++r)
 #pragma unroll
     for (int c = 0; c < CG; ++c) acc[r][c] = 0.0;
 
   if (need) {
-    double ra[A_ELEMS], rb[B_ELEMS];
     const int K = g.K;
     const int nk = (K + BK - 1) / BK;
+    // staged chunk: element pairs (x, y) of each double2 slot
+    double rax[A_V2], ray[A_V2], rbx[B_V2], rby[B_V2];
 
     auto gload = [&](int kc) {
       const int k0 = kc * BK;
+      if (VEC) {
 #pragma unroll
-      for (int e = 0; e < A_ELEMS; ++e) {
-        const int idx = tid + e * kNT;
-        int kk, mm;
-        if (A_KMAJOR) { kk = idx / BM; mm = idx % BM; }
-        else { mm = idx / BK; kk = idx % BK; }
-        const int64_t gm = m0 + mm;
-        const int gk = k0 + kk;
-        double v = 0.0;
-        if (gm < g.M && gk < K)
-          v = A_KMAJOR ? g.A[(int64_t)gk * g.lda + gm] : g.A[gm * g.lda + gk];
-        ra[e] = v;
-      }
+        for (int e = 0; e < A_V2; ++e) {
+          const int idx = tid + e * kNT;
+          double2 t;
+          if (A_KMAJOR) {
+            const int kk = idx / (BM / 2), mm = 2 * (idx % (BM / 2));
+            t = *(const double2*)(g.A + (int64_t)(k0 + kk) * g.lda + m0 + mm);
+          } else {
+            const int mm = idx / (BK / 2), kk = 2 * (idx % (BK / 2));
+            t = *(const double2*)(g.A + (m0 + mm) * g.lda + k0 + kk);
+          }
+          rax[e] = t.x;
+          ray[e] = t.y;
+        }
 #pragma unroll
-      for (int e = 0; e < B_ELEMS; ++e) {
-        const int idx = tid + e * kNT;
-        const int kk = idx / BN, nn = idx % BN;
-        const int64_t gn = n0 + nn;
-        const int gk = k0 + kk;
-        rb[e] = (gn < g.N && gk < K) ? g.B[(int64_t)gk * g.ldb + gn] : 0.0;
+        for (int e = 0; e < B_V2; ++e) {
+          const int idx = tid + e * kNT;
+          const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
+          const double2 t = *(const double2*)(g.B + (int64_t)(k0 + kk) * g.ldb + n0 + nn);
+          rbx[e] = t.x;
+          rby[e] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < A_V2; ++e) {
+          const int idx = tid + e * kNT;
+          int kk, mm, dk, dm;
+          if (A_KMAJOR) { kk = idx / (BM / 2); mm = 2 * (idx % (BM / 2)); dk = 0; dm = 1; }
+          else { mm = idx / (BK / 2); kk = 2 * (idx % (BK / 2)); dk = 1; dm = 0; }
+          double x[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int64_t gm = m0 + mm + u * dm;
+            const int gk = k0 + kk + u * dk;
+            x[u] = (gm < g.M && gk < K) ? (A_KMAJOR ? g.A[(int64_t)gk * g.lda + gm] : g.A[gm * g.lda + gk]) : 0.0;
+          }
+          rax[e] = x[0];
+          ray[e] = x[1];
+        }
+#pragma unroll
+        for (int e = 0; e < B_V2; ++e) {
+          const int idx = tid + e * kNT;
+          const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
+          const int gk = k0 + kk;
+          double x[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int64_t gn = n0 + nn + u;
+            x[u] = (gn < g.N && gk < K) ? g.B[(int64_t)gk * g.ldb + gn] : 0.0;
+          }
+          rbx[e] = x[0];
+          rby[e] = x[1];
+        }
       }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < A_ELEMS; ++e) {
+      for (int e = 0; e < A_V2; ++e) {
         const int idx = tid + e * kNT;
-        int kk, mm;
-        if (A_KMAJOR) { kk = idx / BM; mm = idx % BM; }
-        else { mm = idx / BK; kk = idx % BK; }
-        As[buf][kk * LA + mm] = ra[e];
+        if (A_KMAJOR) {
+          const int kk = idx / (BM / 2), mm = 2 * (idx % (BM / 2));
+          *(double2*)&As[buf][kk * LA + mm] = make_double2(rax[e], ray[e]);
+        } else {
+          const int mm = idx / (BK / 2), kk = 2 * (idx % (BK / 2));
+          As[buf][kk * LA + mm] = rax[e];
+          As[buf][(kk + 1) * LA + mm] = ray[e];
+        }
       }
 #pragma unroll
-      for (int e = 0; e < B_ELEMS; ++e) {
+      for (int e = 0; e < B_V2; ++e) {
         const int idx = tid + e * kNT;
-        const int kk = idx / BN, nn = idx % BN;
-        Bs[buf][kk * LB + nn] = rb[e];
+        const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
+        *(double2*)&Bs[buf][kk * LB + nn] = make_double2(rbx[e], rby[e]);
       }
     };
 
@@ -334,6 +480,7 @@ __global__ void __launch_bounds__(kNT, (BM * BN >= 128 * 128) ? 1 : 2) k_gemm_st
       }
     }
   }
+  }  // tile loop
 }
 
 // ---------------------------------------------------------------------------
@@ -341,10 +488,16 @@ __global__ void __launch_bounds__(kNT, (BM * BN >= 128 * 128) ? 1 : 2) k_gemm_st
 // ---------------------------------------------------------------------------
 hipError_t launch_leaf_inverse(const double* A, int64_t lda, double* P, int64_t ldp, int b, int64_t row0,
                                long long* info, hipStream_t s) {
-  if (b <= 64)
-    hipLaunchKernelGGL((k_leaf_inverse<64>), dim3(1), dim3(kNT), 0, s, A, lda, P, ldp, b, row0, info);
+  if (b <= 8)
+    hipLaunchKernelGGL((k_leaf_inverse<1, 2, 4>), dim3(1), dim3(256), 0, s, A, lda, P, ldp, b, row0, info);
+  else if (b <= 16)
+    hipLaunchKernelGGL((k_leaf_inverse<1, 4, 4>), dim3(1), dim3(256), 0, s, A, lda, P, ldp, b, row0, info);
+  else if (b <= 32)
+    hipLaunchKernelGGL((k_leaf_inverse<1, 8, 4>), dim3(1), dim3(256), 0, s, A, lda, P, ldp, b, row0, info);
+  else if (b <= 64)
+    hipLaunchKernelGGL((k_leaf_inverse<1, 16, 4>), dim3(1), dim3(256), 0, s, A, lda, P, ldp, b, row0, info);
   else
-    hipLaunchKernelGGL((k_leaf_inverse<kLeafMax>), dim3(1), dim3(kNT), 0, s, A, lda, P, ldp, b, row0, info);
+    hipLaunchKernelGGL((k_leaf_inverse<2, 16, 8>), dim3(1), dim3(512), 0, s, A, lda, P, ldp, b, row0, info);
   return hipGetLastError();
 }
 
@@ -370,38 +523,95 @@ hipError_t launch_zero_info(long long* p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Algorithmic flops of one step launch: 2 K per output element that needs the
+// contraction (rows of block p are copies in the Schur update, columns of
+// block p copies in the row panel).
+template <int BM, int BN>
+static double step_flops(const StepArgs& g, int mode) {
+  const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+  auto inband = [&](int64_t tm, int64_t tn) {
+    return (tm >= g.tr0 && tm <= g.tr1) || (tn >= g.tc0 && tn <= g.tc1);
+  };
+  double cnt = 0;
+  for (int64_t tm = 0; tm < TM; ++tm) {
+    const int64_t r0 = tm * BM, r1 = (r0 + BM < g.M) ? r0 + BM : g.M;
+    int64_t rows = r1 - r0;
+    if (mode == MODE_SCHUR) {
+      const int64_t a = (r0 > g.o) ? r0 : g.o, z = (r1 < g.o + g.b) ? r1 : g.o + g.b;
+      if (z > a) rows -= z - a;
+    }
+    for (int64_t tn = 0; tn < TN; ++tn) {
+      if (g.region == 1 && !inband(tm, tn)) continue;
+      if (g.region == 2 && inband(tm, tn)) continue;
+      const int64_t c0 = tn * BN, c1 = (c0 + BN < g.N) ? c0 + BN : g.N;
+      int64_t cols = c1 - c0;
+      if (mode == MODE_ROW) {
+        const int64_t a = (c0 > g.o) ? c0 : g.o, z = (c1 < g.o + g.b) ? c1 : g.o + g.b;
+        if (z > a) cols -= z - a;
+      }
+      cnt += (double)rows * (double)cols;
+    }
+  }
+  return 2.0 * g.K * cnt;
+}
+
 template <int MODE, int BM, int BN, bool AK>
-static hipError_t launch_step(const StepArgs& g, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
-  hipLaunchKernelGGL((k_gemm_step<MODE, BM, BN, AK>), grid, dim3(kNT), 0, s, g);
+static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo, int qb, double* flops,
+                              int slots = 0) {
+  constexpr int BK = 16;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
+  g.region = region;
+  g.tr0 = g.tr1 = g.tc0 = g.tc1 = -1;
+  int64_t T = TM * TN;
+  if (region != 0) {
+    g.tr0 = qo / BM;
+    g.tr1 = (qo + qb - 1) / BM;
+    g.tc0 = qo / BN;
+    g.tc1 = (qo + qb - 1) / BN;
+    if (region == 1) T = (g.tr1 - g.tr0 + 1) * TN + (TM - (g.tr1 - g.tr0 + 1)) * (g.tc1 - g.tc0 + 1);
+  }
+  if (flops) *flops = step_flops<BM, BN>(g, MODE);
+  g.ntiles = T;
+  int64_t G = (T + 7) / 8 * 8;  // multiple of 8 for the XCD-aware tile order
+  if (slots > 0 && G > slots) G = (int64_t)slots / 8 * 8;
+  if (G < 8) G = 8;
+  const bool vec = (g.M % BM == 0) && (g.N % BN == 0) && (g.K % BK == 0) && ((g.lda & 1) == 0) &&
+                   ((g.ldb & 1) == 0) && ((((uintptr_t)g.A) & 15) == 0) && ((((uintptr_t)g.B) & 15) == 0);
+  if (vec)
+    hipLaunchKernelGGL((k_gemm_step<MODE, BM, BN, AK, true>), dim3((unsigned)G), dim3(kNT), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_gemm_step<MODE, BM, BN, AK, false>), dim3((unsigned)G), dim3(kNT), 0, s, g);
   return hipGetLastError();
 }
 
 // Row panel: R (b x n, ldr) = P (b x b, m-major, ldp) * W[o:o+b, :], with R[:, o:o+b] = P.
 hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
-                            double* R, int64_t ldr, hipStream_t s) {
+                            double* R, int64_t ldr, hipStream_t s, double* flops) {
   StepArgs g;
   g.A = P; g.lda = ldp;
   g.B = W + o * ldw; g.ldb = ldw;
   g.W = R; g.ldw = ldr;
   g.R = P; g.ldr = ldp;
   g.M = b; g.N = n; g.K = b; g.o = o; g.b = b;
-  if (n >= 2048) return launch_step<MODE_ROW, 128, 128, false>(g, s);
-  return launch_step<MODE_ROW, 64, 64, false>(g, s);
+  return launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, flops);
 }
 
 // Schur trailing update in place on W using the saved column panel Ct (b x n,
-// k-major) and the row panel R (b x n).
+// k-major) and the row panel R (b x n).  region 0: all tiles; 1: only the
+// tile band covering rows/columns [qo, qo+qb) of the next block; 2: the rest.
+int schur_tile(int64_t n) { return n >= 2048 ? 128 : 64; }
+
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
-                        int64_t o, int b, hipStream_t s) {
+                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots) {
   StepArgs g;
   g.A = Ct; g.lda = ldc;
   g.B = R; g.ldb = ldr;
   g.W = W; g.ldw = ldw;
   g.R = R; g.ldr = ldr;
   g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
-  if (n >= 2048) return launch_step<MODE_SCHUR, 128, 128, true>(g, s);
-  return launch_step<MODE_SCHUR, 64, 64, true>(g, s);
+  if (schur_tile(n) == 128) return launch_step<MODE_SCHUR, 128, 128, true>(g, s, region, qo, qb, flops, slots);
+  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);
 }
 
 }  // namespace binv

@@ -150,3 +150,31 @@ def test_invalid_partition_rejected(gpu):
     A = torch.eye(10, dtype=torch.float64, device="cuda")
     with pytest.raises(binv.BinvError):
         binv.invert(A, part=[3, 3])
+
+
+@pytest.mark.parametrize("n,part", [(1000, [200, 300, 500]), (1536, [512, 512, 512]), (700, None), (2304, None)])
+def test_lookahead_is_bitwise_identical(gpu, n, part):
+    A = wl.diag_dominant(n, 77 + n)
+    X1 = _inv(A, part=part, block=None if part else 256)
+    X2 = _inv(A, part=part, block=None if part else 256, lookahead=False)
+    assert np.array_equal(X1, X2)
+    _check(A, X1)
+
+
+def test_timing_reports_flops(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    n, blk = 2048, 512
+    A = torch.from_numpy(wl.diag_dominant(n, 3)).cuda()
+    ctx = binv.default_context(0)
+    ctx.set_timing(["schur", "band", "row", "pivot"])
+    ctx.get_timing()
+    binv.invert(A, block=blk, ctx=ctx)
+    t = ctx.get_timing()
+    ctx.set_timing([])
+    # every contracted element of the trailing update costs 2 b flops: the
+    # trailing update plus lookahead band cover 2 b (n - b) n per block
+    k = n // blk
+    assert t["schur"][2] + t["band"][2] == pytest.approx(k * 2.0 * blk * (n - blk) * n)
+    assert t["row"][2] == pytest.approx(k * 2.0 * blk * blk * (n - blk))
+    assert t["schur"][1] == k and t["band"][1] == k - 1
