@@ -59,6 +59,9 @@ typedef enum {
 /* Flags for binv_opts.flags. */
 #define BINV_F_SYNC 1u    /* synchronize the stream before returning and report
                              BINV_E_SINGULAR from the device-side info word */
+#define BINV_F_GRAPH 4u  /* batched calls: capture the whole launch sequence in
+                             a HIP graph on first use and replay it (re-captured
+                             when the A, X or info pointers change) */
 #define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only.
                              By default, block p+1's row/column band is updated
                              first, then block p+1's pivot block is inverted
@@ -100,6 +103,41 @@ binv_status binv_destroy(binv_ctx* ctx);
 binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
                         double* X, int64_t ldx, const binv_opts* opts,
                         void* stream, int64_t* d_info);
+
+/* ---------------------------------------------------------------------------
+ * Batched inversion of many small, uneven matrices.
+ *
+ * A plan fixes `count` matrices of orders m[i] in 1..256, packed back to back
+ * in one buffer: matrix i is row-major with leading dimension m[i] and starts
+ * at element sum_{j<i} m[j]^2.  Matrix i is split into k[i] diagonal blocks
+ * (k == NULL: one block) whose orders are part[s_i .. s_i + k[i]) with s_i the
+ * running sum of k (part == NULL: floor(m/k) each, the remainder added one by
+ * one to the last blocks).  Each matrix is inverted by the same blockwise
+ * elimination as binv_invert, with pivoting inside its diagonal blocks only;
+ * blocks larger than 128 of a matrix of order > 128 are split in near-equal
+ * pieces of at most 128.  Host arrays are read during binv_batch_create only.
+ * The plan keeps device copies of its tables and a workspace of about
+ * (128^2 + 256 m) doubles per matrix of order > 128; it belongs to `ctx`'s
+ * device and is released by binv_batch_destroy.
+ * Errors: BINV_E_INVALID for an order outside 1..256, k[i] outside 1..m[i] or
+ * block orders that do not sum to m[i]; BINV_E_NOMEM.
+ * --------------------------------------------------------------------------- */
+typedef struct binv_batch binv_batch;
+
+binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, const int32_t* k,
+                              const int32_t* part, binv_batch** plan);
+binv_status binv_batch_destroy(binv_batch* plan);
+
+/* Number of matrices, packed elements and algorithmic flops (2 sum m^3). */
+binv_status binv_batch_query(const binv_batch* plan, int64_t* count, int64_t* total_elems, double* flops);
+
+/* Invert every matrix of the plan: A and X are device buffers of the plan's
+ * packed size (X == A inverts in place; otherwise they must not overlap).
+ * d_info: device int32[count]; entry i becomes 0, or the 1-based row (within
+ * matrix i) of its first exactly-zero pivot, in which case X's matrix i is
+ * undefined.  flags: BINV_F_GRAPH, BINV_F_SYNC.  Stream-ordered on `stream`. */
+binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, int32_t* d_info, uint32_t flags,
+                                void* stream);
 
 /* Per-phase kernel timing, for measurement.  Phases: */
 #define BINV_PHASE_PIVOT 0   /* pivot-block inversion (leaf kernels, sub-sweeps) */

@@ -24,7 +24,9 @@ BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
+           "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_last_error", "binv_version")
+BINV_F_GRAPH = 4
 PHASES = ("pivot", "row", "schur", "other", "band")
 
 
@@ -74,6 +76,15 @@ def load_library():
     lib.binv_set_timing.restype = ctypes.c_int
     lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
     lib.binv_get_timing.restype = ctypes.c_int
+    lib.binv_batch_create.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.POINTER(P)]
+    lib.binv_batch_create.restype = ctypes.c_int
+    lib.binv_batch_destroy.argtypes = [P]
+    lib.binv_batch_destroy.restype = ctypes.c_int
+    lib.binv_batch_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_double)]
+    lib.binv_batch_query.restype = ctypes.c_int
+    lib.binv_invert_batched.argtypes = [P, P, P, P, ctypes.c_uint32, P]
+    lib.binv_invert_batched.restype = ctypes.c_int
     lib.binv_last_error.argtypes = []
     lib.binv_last_error.restype = ctypes.c_char_p
     lib.binv_version.argtypes = []
@@ -204,3 +215,68 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     del keep
     _check(st)
     return X
+
+
+class Batch:
+    """A plan for inverting many small matrices (orders 1..256) packed back to
+    back in one float64 buffer; matrix i is split into ks[i] diagonal blocks
+    (orders `parts[i]`, or a near-equal split)."""
+
+    def __init__(self, sizes, ks=None, parts=None, ctx=None, device=0):
+        import numpy as np
+        lib = load_library()
+        self.ctx = ctx or default_context(device)
+        self.sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+        n = int(self.sizes.size)
+        self._k = None if ks is None and parts is None else np.ascontiguousarray(
+            [len(p) for p in parts] if parts is not None else ks, dtype=np.int32)
+        self._part = None
+        if parts is not None:
+            self._part = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.int32) for p in parts])
+                                              if n else np.zeros(0, np.int32), dtype=np.int32)
+        h = ctypes.c_void_p()
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None  # noqa: E731
+        _check(lib.binv_batch_create(self.ctx.handle, n, ptr(self.sizes), ptr(self._k), ptr(self._part),
+                                     ctypes.byref(h)))
+        self._h = h
+        cnt, tot, fl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib.binv_batch_query(self._h, ctypes.byref(cnt), ctypes.byref(tot), ctypes.byref(fl)))
+        self.count, self.total_elems, self.flops = int(cnt.value), int(tot.value), float(fl.value)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes.astype(np.int64) ** 2)])[:-1] if n else np.zeros(0)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().binv_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def invert(self, A, out=None, info=None, graph=True, sync=True, inplace=False):
+        """Invert every matrix of the packed float64 CUDA buffer A; returns (X, info)."""
+        import torch
+        if A.dtype != torch.float64 or not A.is_cuda or A.numel() != self.total_elems or not A.is_contiguous():
+            raise ValueError("A must be a contiguous float64 CUDA buffer of the plan's packed size")
+        X = A if inplace else (out if out is not None else torch.empty_like(A))
+        if info is None:
+            info = torch.empty(max(self.count, 1), dtype=torch.int32, device=A.device)
+        flags = (BINV_F_GRAPH if graph else 0) | (BINV_F_SYNC if sync else 0)
+        with torch.cuda.device(A.device):
+            st = load_library().binv_invert_batched(self._h, ctypes.c_void_p(A.data_ptr()),
+                                                    ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+                                                    flags, _stream_handle(torch, A.device.index or 0))
+        _check(st)
+        return X, info
+
+    def pack(self, mats):
+        """Pack a list of square numpy matrices into one flat float64 array."""
+        import numpy as np
+        return np.concatenate([np.ascontiguousarray(M, dtype=np.float64).ravel() for M in mats]) \
+            if len(mats) else np.zeros(0)
+
+    def unpack(self, flat):
+        """Split a flat array (numpy) back into the plan's matrices."""
+        return [flat[o:o + m * m].reshape(m, m) for o, m in zip(self.offsets, self.sizes)]

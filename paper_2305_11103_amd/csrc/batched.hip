@@ -1,0 +1,222 @@
+// Batched inversion of many small, uneven matrices (orders up to 256).
+//
+// Every matrix keeps its own partition into diagonal blocks.  Eliminating the
+// columns of diagonal block p one at a time, with the pivot of each column
+// searched only among the not-yet-used rows of block p, performs exactly the
+// row operations of one step of the blockwise sweep (Eq. (a) of §3 applied in
+// place, §4.2): the Gauss-Jordan inversion of the pivot block P = W_pp^-1
+// (pivoting inside the block), then W_pj <- P W_pj and the Schur update
+// W_ij <- W_ij - W_ip P W_pj.  So a matrix of order <= 128 is inverted by one
+// register-resident kernel pass with that block-restricted pivoting.
+//
+// Register layout per matrix (as in the leaf kernel of kernels.hip): NWV waves,
+// wave w owns columns [w CPW, (w+1) CPW), lane l owns rows l + 64 h (h < RPL);
+// a workgroup holds SUB independent matrices, one per group of NWV waves.  The
+// matrix is padded with an identity to NB = NWV*CPW (the padding forms a last
+// diagonal block of its own).
+//
+// Pivot rows are stored unscaled: when row r becomes the pivot of column c
+// (value pv, q = 1/pv), its stored values stay as they are and its scale
+// becomes q (its column-c slot is set to 1, i.e. q / q).  Any later update of
+// a row subtracts (its stored multiplier) x (true scaled pivot row), which is
+// the true update divided by that row's scale, so every row is rescaled once
+// at the end.  This saves one multiply per element per column.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "binv_internal.h"
+
+namespace binv {
+
+
+__device__ __forceinline__ double bread_f64(double x, int l) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int RPL, int CPW, int NWV, int SUB>
+__global__ void __launch_bounds__(64 * NWV * SUB)
+k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const SmallMat* __restrict__ mats,
+                const int32_t* __restrict__ order, int64_t count, const int32_t* __restrict__ bounds,
+                int32_t* __restrict__ info) {
+  constexpr int NB = NWV * CPW;
+  static_assert(NB <= 64 * RPL, "columns exceed rows");
+  __shared__ double colbuf[SUB][2][64 * RPL];
+  __shared__ int s_r[SUB][2];
+  __shared__ double s_pv[SUB][2];
+  __shared__ int piv_row[SUB][NB];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int gwave = tid >> 6;
+  const int sub = gwave / NWV;          // which matrix of the workgroup
+  const int wave = gwave % NWV;         // wave within the matrix group
+  const int64_t slot = (int64_t)blockIdx.x * SUB + sub;
+  const bool active = slot < count;     // uniform per wave group
+  SmallMat mt;
+  mt.off = 0; mt.m = 0; mt.nb = 0; mt.bnd = 0; mt.id = 0;
+  if (active) mt = mats[order[slot]];
+  const int m = mt.m;
+  const int cbase = wave * CPW;
+
+  double v[RPL][CPW];
+  double scale[RPL];
+  bool used[RPL];
+  int step_of[RPL];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int row = lane + 64 * h;
+    used[h] = row >= NB;
+    step_of[h] = 0;
+    scale[h] = 1.0;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = cbase + j;
+      v[h][j] = (row < m && col < m) ? A[mt.off + (int64_t)row * m + col] : (row == col ? 1.0 : 0.0);
+    }
+  }
+
+  // current diagonal block [bs, be) of the column being eliminated
+  int blk = 0;
+  int bs = 0;
+  int be = (mt.nb > 0) ? bounds[mt.bnd + 1] : NB;
+  bool singular = false;
+  for (int cw = 0; cw < NWV; ++cw) {
+    const bool owner = (wave == cw);
+#pragma unroll
+    for (int t = 0; t < CPW; ++t) {
+      const int c = cw * CPW + t;
+      const int buf = c & 1;
+      if (c == be) {  // uniform: advance to the next diagonal block (or padding)
+        bs = be;
+        ++blk;
+        be = (blk < mt.nb) ? bounds[mt.bnd + blk + 1] : NB;
+      }
+      if (owner) {
+        unsigned long long key[RPL];
+        unsigned long long kmax = 0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          const int row = lane + 64 * h;
+          const bool cand = !used[h] && row >= bs && row < be;
+          key[h] = cand ? (unsigned long long)__double_as_longlong(fabs(v[h][t])) + 1ULL : 0ULL;
+          kmax = key[h] > kmax ? key[h] : kmax;
+        }
+        const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
+        const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
+        kmax = ((unsigned long long)hi << 32) | lo;
+        int r = 64 * RPL;
+#pragma unroll
+        for (int h = RPL - 1; h >= 0; --h) {
+          const unsigned long long mk = __ballot(key[h] == kmax);
+          if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
+        }
+        double pv = 0.0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          colbuf[sub][buf][lane + 64 * h] = v[h][t];
+          if ((r >> 6) == h) pv = bread_f64(v[h][t], r & 63);
+        }
+        if (lane == 0) {
+          s_r[sub][buf] = r;
+          s_pv[sub][buf] = pv;
+        }
+      }
+      __syncthreads();
+      const int r = s_r[sub][buf];
+      const double pv = s_pv[sub][buf];
+      if (pv == 0.0 && !singular) {
+        if (active && wave == 0 && lane == 0 && c < m) info[mt.id] = c + 1;
+        singular = true;
+      }
+      const double q = 1.0 / pv;
+      const int rl = __builtin_amdgcn_readfirstlane(r & 63);
+      const int rh = (RPL == 1) ? 0 : __builtin_amdgcn_readfirstlane(r >> 6);
+      double sp[CPW];
+      if (RPL == 1 || rh == 0) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[0][j], rl) * q;
+      } else {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[RPL - 1][j], rl) * q;
+      }
+      sp[t] = owner ? q : sp[t];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        const int row = lane + 64 * h;
+        const bool isr = (row == r);
+        const double f = isr ? 0.0 : colbuf[sub][buf][row];
+        v[h][t] = owner ? (isr ? 1.0 : 0.0) : v[h][t];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) v[h][j] = fma(-f, sp[j], v[h][j]);
+        used[h] = used[h] || isr;
+        step_of[h] = isr ? c : step_of[h];
+        scale[h] = isr ? q : scale[h];
+      }
+      if (wave == 0 && lane == 0) piv_row[sub][c] = r;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  if (!singular && wave == 0 && lane == 0) info[mt.id] = 0;
+  if (singular) return;
+  // X^-1[step_of(row)][piv_row[col]] = scale(row) * W[row][col]
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int row = lane + 64 * h;
+    if (row >= m) continue;
+    double* dst = X + mt.off + (int64_t)step_of[h] * m;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = cbase + j;
+      if (col < m) dst[piv_row[sub][col]] = v[h][j] * scale[h];
+    }
+  }
+}
+
+hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
+                             int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  switch (tier) {
+    case 0: {  // m <= 8: four matrices per workgroup, one wave each
+      const unsigned g = (unsigned)((count + 3) / 4);
+      hipLaunchKernelGGL((k_small_inverse<1, 8, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds, info);
+      break;
+    }
+    case 1: {  // m <= 16
+      const unsigned g = (unsigned)((count + 3) / 4);
+      hipLaunchKernelGGL((k_small_inverse<1, 16, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds,
+                         info);
+      break;
+    }
+    case 2: {  // m <= 32
+      const unsigned g = (unsigned)((count + 3) / 4);
+      hipLaunchKernelGGL((k_small_inverse<1, 32, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds,
+                         info);
+      break;
+    }
+    case 3: {  // m <= 64: four waves per matrix
+      hipLaunchKernelGGL((k_small_inverse<1, 16, 4, 1>), dim3((unsigned)count), dim3(256), 0, s, A, X, mats, order,
+                         count, bounds, info);
+      break;
+    }
+    case 4: {  // m <= 128: eight waves per matrix, two rows per lane
+      hipLaunchKernelGGL((k_small_inverse<2, 16, 8, 1>), dim3((unsigned)count), dim3(512), 0, s, A, X, mats, order,
+                         count, bounds, info);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Largest order handled by each small tier.
+int small_tier_limit(int tier) {
+  static const int lim[5] = {8, 16, 32, 64, 128};
+  return (tier >= 0 && tier < 5) ? lim[tier] : 0;
+}
+
+}  // namespace binv

@@ -1,0 +1,372 @@
+// C ABI of the batched inversion (binv_batch_*; declared in include/binv.h).
+//
+// A plan fixes the orders and diagonal-block partitions of a batch of small
+// matrices packed back to back.  Matrices of order <= 128 go to one of five
+// register-resident tiers (k_small_inverse: one pass, pivoting restricted to
+// each diagonal block); orders 129..256 are swept block by block with batched
+// step kernels (one workgroup per matrix: pivot leaf, column-panel save, row
+// panel, Schur update), the same Eq. (a) step as the single-matrix path.  All
+// job tables live on the device, so a run is a fixed sequence of launches that
+// is captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "binv_internal.h"
+
+namespace {
+
+constexpr int kSmallTiers = 5;
+constexpr int kBlockMax = 128;  // largest diagonal block of the swept tier
+
+binv_status bfail(binv_status st, const std::string& msg) {
+  binv::set_error(msg);
+  return st;
+}
+
+#define BHIP(expr)                                                                      \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return bfail(BINV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+binv_status upload(const std::vector<T>& h, void** d) {
+  *d = nullptr;
+  if (h.empty()) return BINV_OK;
+  if (hipMalloc(d, sizeof(T) * h.size()) != hipSuccess) {
+    *d = nullptr;
+    return bfail(BINV_E_NOMEM, "hipMalloc for the batch plan failed");
+  }
+  BHIP(hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  return BINV_OK;
+}
+
+}  // namespace
+
+// One step of the swept tier: the jobs of all matrices that have a block s.
+struct SweptStep {
+  int64_t first = 0, count = 0;  // range in the per-step job arrays
+  int bmax = 0;
+};
+
+struct binv_batch {
+  binv_ctx* ctx = nullptr;
+  int device = 0;
+  int64_t count = 0;
+  int64_t total = 0;      // packed elements
+  double flops = 0;       // 2 sum m^3
+  std::vector<int64_t> off;
+  std::vector<int32_t> m;
+  // small tiers
+  int64_t tier_first[kSmallTiers] = {0}, tier_count[kSmallTiers] = {0};
+  void* d_mats = nullptr;    // SmallMat per matrix (all matrices)
+  void* d_order = nullptr;   // matrix indices grouped by tier
+  void* d_bounds = nullptr;  // diagonal-block boundaries
+  // swept tier (orders 129..256)
+  std::vector<SweptStep> steps;
+  std::vector<int32_t> swept;     // matrix indices
+  std::vector<int64_t> ws_off;    // workspace offset (elements) per swept matrix
+  int64_t ws_elems = 0;
+  void* d_ws = nullptr;
+  // job tables are built per (A, X, info) binding; rebuilt when they change
+  const void* bound_A = nullptr;
+  void* bound_X = nullptr;
+  void* bound_info = nullptr;
+  void* d_leaf = nullptr;
+  void* d_col = nullptr;
+  void* d_row = nullptr;
+  void* d_schur = nullptr;
+  // graph of the whole run for the current binding
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  std::vector<int32_t> bounds_host;
+  std::vector<int32_t> bnd_index;
+};
+
+namespace {
+
+void free_bindings(binv_batch* b) {
+  for (void** p : {&b->d_leaf, &b->d_col, &b->d_row, &b->d_schur}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->bound_A = nullptr;
+  b->bound_X = nullptr;
+  b->bound_info = nullptr;
+}
+
+// Build the per-step job tables of the swept tier for buffers (A, X, info).
+binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
+  free_bindings(b);
+  std::vector<binv::LeafJob> leaf;
+  std::vector<binv::ColJob> col;
+  std::vector<binv::StepArgs> row, schur;
+  double* ws = (double*)b->d_ws;
+  for (size_t s = 0; s < b->steps.size(); ++s) {
+    for (size_t t = 0; t < b->swept.size(); ++t) {
+      const int i = b->swept[t];
+      const int mi = b->m[i];
+      const int bi = b->bnd_index[i];
+      const int nb = b->bnd_index[i + 1] - bi - 1;
+      if ((int)s >= nb) continue;
+      const int o = b->bounds_host[bi + s];
+      const int bs = b->bounds_host[bi + s + 1] - o;
+      const double* Win = (s == 0 ? A : (const double*)X) + b->off[i];
+      double* Wout = X + b->off[i];
+      double* P = ws + b->ws_off[t];
+      double* Ct = P + kBlockMax * kBlockMax;
+      double* R = Ct + (int64_t)kBlockMax * mi;
+      binv::LeafJob lj;
+      lj.A = Win + (int64_t)o * mi + o; lj.lda = mi; lj.P = P; lj.ldp = bs; lj.b = bs; lj.row0 = o;
+      lj.info = info + i;
+      leaf.push_back(lj);
+      binv::ColJob cj;
+      cj.W = Win; cj.ldw = mi; cj.n = mi; cj.o = o; cj.b = bs; cj.Ct = Ct; cj.ldc = mi;
+      col.push_back(cj);
+      binv::StepArgs ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.A = P; ra.lda = bs; ra.B = Win + (int64_t)o * mi; ra.ldb = mi; ra.W = R; ra.ldw = mi;
+      ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = mi; ra.K = bs; ra.o = o; ra.b = bs;
+      row.push_back(ra);
+      binv::StepArgs sa;
+      std::memset(&sa, 0, sizeof(sa));
+      sa.A = Ct; sa.lda = mi; sa.B = R; sa.ldb = mi; sa.W = Wout; sa.ldw = mi; sa.Win = Win; sa.ldwin = mi;
+      sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs;
+      schur.push_back(sa);
+    }
+  }
+  binv_status st;
+  if ((st = upload(leaf, &b->d_leaf)) != BINV_OK) return st;
+  if ((st = upload(col, &b->d_col)) != BINV_OK) return st;
+  if ((st = upload(row, &b->d_row)) != BINV_OK) return st;
+  if ((st = upload(schur, &b->d_schur)) != BINV_OK) return st;
+  b->bound_A = A;
+  b->bound_X = X;
+  b->bound_info = info;
+  return BINV_OK;
+}
+
+// Enqueue the whole batched inversion on stream s.
+binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hipStream_t s) {
+  // every matrix's info word starts at 0; the small tiers overwrite theirs
+  BHIP(binv::launch_fill_i32(info, b->count, 0, s));
+  for (int t = 0; t < kSmallTiers; ++t)
+    BHIP(binv::launch_small_tier(t, A, X, (const binv::SmallMat*)b->d_mats,
+                                 (const int32_t*)b->d_order + b->tier_first[t], b->tier_count[t],
+                                 (const int32_t*)b->d_bounds, info, s));
+  for (const SweptStep& st : b->steps) {
+    BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + st.first, st.count, st.bmax, s));
+    BHIP(binv::launch_col_save_batched((const binv::ColJob*)b->d_col + st.first, st.count, s));
+    BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, s));
+    BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, s));
+  }
+  return BINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, const int32_t* k, const int32_t* part,
+                              binv_batch** plan) {
+  if (!plan) return bfail(BINV_E_INVALID, "plan is NULL");
+  *plan = nullptr;
+  if (!ctx) return bfail(BINV_E_INVALID, "ctx is NULL");
+  if (count < 0 || (count > 0 && !m)) return bfail(BINV_E_INVALID, "bad count or NULL orders");
+  binv_batch* b = new (std::nothrow) binv_batch();
+  if (!b) return bfail(BINV_E_NOMEM, "out of host memory");
+  b->ctx = ctx;
+  (void)hipGetDevice(&b->device);
+  b->count = count;
+  b->off.resize(count);
+  b->m.resize(count);
+  b->bnd_index.resize(count + 1);
+  std::vector<binv::SmallMat> mats(count);
+  std::vector<std::vector<int32_t>> tiers(kSmallTiers);
+  int64_t off = 0, poff = 0;
+  int maxsteps = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int mi = m[i];
+    if (mi < 1 || mi > 256) {
+      delete b;
+      return bfail(BINV_E_INVALID, "matrix order outside 1..256 at index " + std::to_string(i));
+    }
+    const int ki = k ? k[i] : 1;
+    if (ki < 1 || ki > mi) {
+      delete b;
+      return bfail(BINV_E_INVALID, "block count outside 1..m at index " + std::to_string(i));
+    }
+    b->off[i] = off;
+    b->m[i] = mi;
+    b->bnd_index[i] = (int32_t)b->bounds_host.size();
+    // diagonal blocks: given orders, or floor(m/k) with the remainder on the last blocks
+    std::vector<int> ord(ki);
+    if (part) {
+      int64_t sum = 0;
+      for (int j = 0; j < ki; ++j) {
+        ord[j] = part[poff + j];
+        if (ord[j] < 1) {
+          delete b;
+          return bfail(BINV_E_INVALID, "non-positive block order at index " + std::to_string(i));
+        }
+        sum += ord[j];
+      }
+      poff += ki;
+      if (sum != mi) {
+        delete b;
+        return bfail(BINV_E_INVALID, "block orders do not sum to m at index " + std::to_string(i));
+      }
+    } else {
+      const int base = mi / ki, rem = mi - base * ki;
+      for (int j = 0; j < ki; ++j) ord[j] = base + (j >= ki - rem ? 1 : 0);
+    }
+    // the swept tier needs blocks of at most 128: split larger ones in halves
+    std::vector<int> fin;
+    for (int x : ord) {
+      if (mi > 128 && x > kBlockMax) {
+        const int pieces = (x + kBlockMax - 1) / kBlockMax;
+        for (int q = 0; q < pieces; ++q) fin.push_back(x / pieces + (q >= pieces - x % pieces ? 1 : 0));
+      } else {
+        fin.push_back(x);
+      }
+    }
+    int acc = 0;
+    b->bounds_host.push_back(0);
+    for (int x : fin) {
+      acc += x;
+      b->bounds_host.push_back(acc);
+    }
+    mats[i].off = off;
+    mats[i].m = mi;
+    mats[i].nb = (int)fin.size();
+    mats[i].bnd = b->bnd_index[i];
+    mats[i].id = (int)i;
+    if (mi <= 128) {
+      int t = 0;
+      while (mi > binv::small_tier_limit(t)) ++t;
+      tiers[t].push_back((int32_t)i);
+    } else {
+      b->swept.push_back((int32_t)i);
+      maxsteps = std::max(maxsteps, (int)fin.size());
+    }
+    off += (int64_t)mi * mi;
+    b->flops += 2.0 * mi * (double)mi * mi;
+  }
+  b->bnd_index[count] = (int32_t)b->bounds_host.size();
+  b->total = off;
+  // largest matrices first within each tier
+  std::vector<int32_t> order;
+  for (int t = 0; t < kSmallTiers; ++t) {
+    std::stable_sort(tiers[t].begin(), tiers[t].end(), [&](int32_t x, int32_t y) { return b->m[x] > b->m[y]; });
+    b->tier_first[t] = (int64_t)order.size();
+    b->tier_count[t] = (int64_t)tiers[t].size();
+    order.insert(order.end(), tiers[t].begin(), tiers[t].end());
+  }
+  std::stable_sort(b->swept.begin(), b->swept.end(), [&](int32_t x, int32_t y) { return b->m[x] > b->m[y]; });
+  int64_t ws = 0;
+  for (int32_t i : b->swept) {
+    b->ws_off.push_back(ws);
+    ws += (int64_t)kBlockMax * kBlockMax + 2LL * kBlockMax * b->m[i];
+  }
+  b->ws_elems = ws;
+  int64_t first = 0;
+  for (int s = 0; s < maxsteps; ++s) {
+    SweptStep st;
+    st.first = first;
+    for (int32_t i : b->swept) {
+      const int bi = b->bnd_index[i];
+      const int nb = b->bnd_index[i + 1] - bi - 1;
+      if (s < nb) {
+        ++st.count;
+        st.bmax = std::max(st.bmax, b->bounds_host[bi + s + 1] - b->bounds_host[bi + s]);
+      }
+    }
+    first += st.count;
+    b->steps.push_back(st);
+  }
+  binv_status st;
+  if ((st = upload(mats, &b->d_mats)) != BINV_OK || (st = upload(order, &b->d_order)) != BINV_OK ||
+      (st = upload(b->bounds_host, &b->d_bounds)) != BINV_OK) {
+    binv_batch_destroy(b);
+    return st;
+  }
+  if (ws > 0 && hipMalloc(&b->d_ws, sizeof(double) * (size_t)ws) != hipSuccess) {
+    b->d_ws = nullptr;
+    binv_batch_destroy(b);
+    return bfail(BINV_E_NOMEM, "hipMalloc of the batch workspace failed");
+  }
+  *plan = b;
+  return BINV_OK;
+}
+
+binv_status binv_batch_destroy(binv_batch* b) {
+  if (!b) return BINV_OK;
+  if (b->cap) (void)hipStreamSynchronize(b->cap);
+  free_bindings(b);
+  for (void* p : {b->d_mats, b->d_order, b->d_bounds, b->d_ws})
+    if (p) (void)hipFree(p);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return BINV_OK;
+}
+
+binv_status binv_batch_query(const binv_batch* b, int64_t* count, int64_t* total_elems, double* flops) {
+  if (!b) return bfail(BINV_E_INVALID, "plan is NULL");
+  if (count) *count = b->count;
+  if (total_elems) *total_elems = b->total;
+  if (flops) *flops = b->flops;
+  return BINV_OK;
+}
+
+binv_status binv_invert_batched(binv_batch* b, const double* A, double* X, int32_t* d_info, uint32_t flags,
+                                void* stream) {
+  if (!b) return bfail(BINV_E_INVALID, "plan is NULL");
+  if (b->count == 0) return BINV_OK;
+  if (!A || !X || !d_info) return bfail(BINV_E_INVALID, "A, X and d_info must be device pointers");
+  if (A != X) {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + b->total);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + b->total);
+    if (a0 < x1 && x0 < a1) return bfail(BINV_E_INVALID, "A and X overlap without being the same buffer");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (b->bound_A != A || b->bound_X != X || b->bound_info != d_info) {
+    binv_status st = bind(b, A, X, d_info);
+    if (st != BINV_OK) return st;
+  }
+  if (flags & BINV_F_GRAPH) {
+    if (!b->exec) {
+      if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      binv_status st = enqueue(b, A, X, d_info, b->cap);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(b->cap, &g);
+      if (st != BINV_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return bfail(BINV_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      b->graph = g;
+      BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    BHIP(hipGraphLaunch(b->exec, s));
+  } else {
+    binv_status st = enqueue(b, A, X, d_info, s);
+    if (st != BINV_OK) return st;
+  }
+  if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));
+  return BINV_OK;
+}
+
+}  // extern "C"

@@ -16,23 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/binv.h"
-
-namespace binv {
-hipError_t launch_leaf_inverse(const double* A, int64_t lda, double* P, int64_t ldp, int b, int64_t row0,
-                               long long* info, hipStream_t s);
-hipError_t launch_col_save(const double* W, int64_t ldw, int64_t n, int64_t o, int b, double* Ct, int64_t ldc,
-                           hipStream_t s);
-hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
-                         hipStream_t s);
-hipError_t launch_zero_info(long long* p, hipStream_t s);
-hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
-                            double* R, int64_t ldr, hipStream_t s, double* flops);
-hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
-                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
-constexpr int kLeafMax = 128;
-constexpr int kSubBlock = 64;
-}  // namespace binv
+#include "binv_internal.h"
 
 namespace {
 
@@ -42,6 +26,12 @@ binv_status fail(binv_status st, const std::string& msg) {
   g_err = msg;
   return st;
 }
+
+}  // namespace
+
+void binv::set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                      \
   do {                                                                                     \

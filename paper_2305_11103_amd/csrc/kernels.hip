@@ -25,11 +25,13 @@
 // column l%16) of that 4 x 16 tile.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
+
+#include "binv_internal.h"
 
 namespace binv {
 
 constexpr int kNT = 256;        // threads per workgroup in the GEMM and leaf kernels
-constexpr int kLeafMax = 128;   // largest pivot block the LDS leaf kernel holds
 
 // ---------------------------------------------------------------------------
 // Leaf: Gauss-Jordan with partial pivoting on a b x b block held in registers.
@@ -57,10 +59,14 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-template <int RPL, int CPW, int NWV>
-__global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restrict__ A, int64_t lda,
-                                                           double* __restrict__ P, int64_t ldp, int b,
-                                                           int64_t row0, long long* info) {
+__device__ __forceinline__ void record_singular(long long* info, long long row) {
+  atomicCAS((unsigned long long*)info, 0ULL, (unsigned long long)row);
+}
+__device__ __forceinline__ void record_singular(int* info, long long row) { atomicCAS(info, 0, (int)row); }
+
+template <int RPL, int CPW, int NWV, class InfoT>
+__device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t lda, double* __restrict__ P,
+                                          int64_t ldp, int b, int64_t row0, InfoT* info) {
   constexpr int NB = NWV * CPW;  // the block is padded to NB x NB with an identity
   static_assert(NB <= 64 * RPL, "columns exceed rows");
   __shared__ double colbuf[2][64 * RPL];
@@ -136,7 +142,7 @@ __global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restr
       if (pv == 0.0 && !singular) {
         // exactly-zero pivot: record it; the arithmetic runs on (inf/nan) and
         // the result is not stored
-        if (tid == 0) atomicCAS((unsigned long long*)info, 0ULL, (unsigned long long)(row0 + c + 1));
+        if (tid == 0) record_singular(info, (long long)(row0 + c + 1));
         singular = true;
       }
       const double q = 1.0 / pv;
@@ -187,6 +193,21 @@ __global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restr
   }
 }
 
+template <int RPL, int CPW, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restrict__ A, int64_t lda,
+                                                           double* __restrict__ P, int64_t ldp, int b,
+                                                           int64_t row0, long long* info) {
+  leaf_body<RPL, CPW, NWV>(A, lda, P, ldp, b, row0, info);
+}
+
+// Batched leaf: workgroup i inverts jobs[i].
+
+template <int RPL, int CPW, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_leaf_inverse_batched(const LeafJob* __restrict__ jobs) {
+  const LeafJob j = jobs[blockIdx.x];
+  leaf_body<RPL, CPW, NWV>(j.A, j.lda, j.P, j.ldp, j.b, (int64_t)j.row0, j.info);
+}
+
 // ---------------------------------------------------------------------------
 // Column panel save: Ct[t][i] = W[i][o + t], t < b, i < n (tiled transpose).
 // ---------------------------------------------------------------------------
@@ -209,6 +230,18 @@ __global__ void __launch_bounds__(256) k_col_save(const double* __restrict__ W, 
   }
 }
 
+// Batched column-panel save: workgroup i copies panel i (small matrices).
+
+__global__ void __launch_bounds__(256) k_col_save_batched(const ColJob* __restrict__ jobs) {
+  const ColJob j = jobs[blockIdx.x];
+  const int64_t total = (int64_t)j.b * j.n;
+  for (int64_t e = threadIdx.x; e < total; e += 256) {
+    const int64_t i = e / j.b;
+    const int t = (int)(e - i * j.b);
+    j.Ct[(int64_t)t * j.ldc + i] = j.W[i * j.ldw + j.o + t];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2-D copy (out-of-place calls start from a copy of A).
 // ---------------------------------------------------------------------------
@@ -224,6 +257,10 @@ __global__ void k_zero_i64(long long* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // GEMM step kernel.
 // ---------------------------------------------------------------------------
@@ -231,29 +268,6 @@ enum { MODE_ROW = 0, MODE_SCHUR = 1 };
 
 typedef double dbl;
 
-struct StepArgs {
-  // operand A of the contraction, k-major (A_km[t][m]) or m-major (A_mm[m][t])
-  const double* A;
-  int64_t lda;
-  // operand B, k-major: B[t][j]
-  const double* B;
-  int64_t ldb;
-  // output: MODE_ROW -> R (ldr); MODE_SCHUR -> W in place (ldw) and copy rows from R
-  double* W;
-  int64_t ldw;
-  const double* R;   // row panel (MODE_SCHUR) or pivot inverse P (MODE_ROW, ld = ldp)
-  int64_t ldr;
-  int64_t M, N;      // output extent
-  int K;             // contraction length (= b)
-  int64_t o;         // first row/column of block p
-  int b;             // order of block p
-  // tile subset (MODE_SCHUR): 0 = every tile; 1 = the band of tile-rows
-  // [tr0, tr1] and tile-columns [tc0, tc1] (the next block's rows and
-  // columns); 2 = every tile outside that band.
-  int region;
-  int64_t tr0, tr1, tc0, tc1;
-  int64_t ntiles;    // tiles enumerated by the region (before band skipping)
-};
 
 // Tile order: the grid is 1-D and persistent.  Workgroups are dealt to the 8
 // XCDs round-robin (workgroup g runs on XCD g % 8), so XCD x owns the
@@ -292,34 +306,41 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64
   return true;
 }
 
+// GEMM tile configuration.  NWM x NWN waves per workgroup, each owning a
+// (BM/NWM) x (BN/NWN) sub-tile; K is consumed in LDS chunks of BK.
 // VEC: every tile is interior, K is a multiple of BK and rows are 16-byte
 // aligned, so global loads are unguarded double2 loads; otherwise loads are
 // guarded element by element.
-template <int MODE, int BM, int BN, bool A_KMAJOR, bool VEC>
-__global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
-  constexpr int BK = 16;
-  constexpr int PAD = 4;
-  constexpr int LA = BM + PAD;
-  constexpr int LB = BN + PAD;
-  constexpr int WM = BM / 2, WN = BN / 2;   // 2 x 2 waves
-  constexpr int RG = WM / 4, CG = WN / 16;  // 4x16 MFMA tiles per wave
-  constexpr int A_V2 = BK * BM / 2 / kNT;   // per-thread double2 loads per chunk
-  constexpr int B_V2 = BK * BN / 2 / kNT;
-  static_assert(A_V2 * 2 * kNT == BK * BM && B_V2 * 2 * kNT == BK * BN, "tile/thread mismatch");
-  __shared__ double As[2][BK * LA];
-  __shared__ double Bs[2][BK * LB];
+template <int BM_, int BN_, int NWM_, int NWN_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, NWM = NWM_, NWN = NWN_;
+  static constexpr int NT = 64 * NWM * NWN;
+  static constexpr int BK = 16;
+  static constexpr int PAD = 4;
+  static constexpr int LA = BM + PAD;
+  static constexpr int LB = BN + PAD;
+};
 
-  const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-  const int64_t T8 = (g.ntiles + 7) / 8;
-  const int64_t xcd = blockIdx.x & 7, per = (int64_t)gridDim.x >> 3;
-  for (int64_t tl = (int64_t)blockIdx.x >> 3; tl < T8; tl += per) {
-  int64_t tm, tn;
-  if (!tile_of<8>(xcd * T8 + tl, TM, TN, tm, tn, g.region, g.tr0, g.tr1, g.tc0, g.tc1)) continue;
+// One output tile (tm, tn) of a step GEMM.
+template <int MODE, class C, bool A_KMAJOR, bool VEC>
+__device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t tn,
+                                          double (&As)[2][C::BK * C::LA], double (&Bs)[2][C::BK * C::LB]) {
+  constexpr int BM = C::BM, BN = C::BN, NWM = C::NWM, NWN = C::NWN, NT = C::NT, BK = C::BK;
+  constexpr int LA = C::LA, LB = C::LB;
+  constexpr int WM = BM / NWM, WN = BN / NWN;
+  constexpr int RG = WM / 4, CG = WN / 16;  // 4x16 MFMA tiles per wave
+  constexpr int A_V2 = BK * BM / 2 / NT;    // per-thread double2 loads per chunk
+  constexpr int B_V2 = BK * BN / 2 / NT;
+  static_assert(A_V2 * 2 * NT == BK * BM && B_V2 * 2 * NT == BK * BN, "tile/thread mismatch");
+  static_assert(WM % 4 == 0 && WN % 16 == 0, "wave tile must be whole 4x16 MFMA tiles");
+  // full unroll of the k4 loop hoists every fragment load; at 4 waves per SIMD
+  // (<= 128 VGPRs) that spills, so the 8-wave form keeps it rolled
+  constexpr int KU = (NWM * NWN >= 8) ? 1 : BK / 4;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
   const int64_t m0 = tm * BM;
   const int64_t n0 = tn * BN;
   const int64_t o = g.o;
@@ -350,7 +371,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
       if (VEC) {
 #pragma unroll
         for (int e = 0; e < A_V2; ++e) {
-          const int idx = tid + e * kNT;
+          const int idx = tid + e * NT;
           double2 t;
           if (A_KMAJOR) {
             const int kk = idx / (BM / 2), mm = 2 * (idx % (BM / 2));
@@ -364,7 +385,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
         }
 #pragma unroll
         for (int e = 0; e < B_V2; ++e) {
-          const int idx = tid + e * kNT;
+          const int idx = tid + e * NT;
           const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
           const double2 t = *(const double2*)(g.B + (int64_t)(k0 + kk) * g.ldb + n0 + nn);
           rbx[e] = t.x;
@@ -373,7 +394,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
       } else {
 #pragma unroll
         for (int e = 0; e < A_V2; ++e) {
-          const int idx = tid + e * kNT;
+          const int idx = tid + e * NT;
           int kk, mm, dk, dm;
           if (A_KMAJOR) { kk = idx / (BM / 2); mm = 2 * (idx % (BM / 2)); dk = 0; dm = 1; }
           else { mm = idx / (BK / 2); kk = 2 * (idx % (BK / 2)); dk = 1; dm = 0; }
@@ -389,7 +410,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
         }
 #pragma unroll
         for (int e = 0; e < B_V2; ++e) {
-          const int idx = tid + e * kNT;
+          const int idx = tid + e * NT;
           const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
           const int gk = k0 + kk;
           double x[2];
@@ -406,7 +427,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
     auto sstore = [&](int buf) {
 #pragma unroll
       for (int e = 0; e < A_V2; ++e) {
-        const int idx = tid + e * kNT;
+        const int idx = tid + e * NT;
         if (A_KMAJOR) {
           const int kk = idx / (BM / 2), mm = 2 * (idx % (BM / 2));
           *(double2*)&As[buf][kk * LA + mm] = make_double2(rax[e], ray[e]);
@@ -418,7 +439,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
       }
 #pragma unroll
       for (int e = 0; e < B_V2; ++e) {
-        const int idx = tid + e * kNT;
+        const int idx = tid + e * NT;
         const int kk = idx / (BN / 2), nn = 2 * (idx % (BN / 2));
         *(double2*)&Bs[buf][kk * LB + nn] = make_double2(rbx[e], rby[e]);
       }
@@ -435,7 +456,7 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
       if (kc + 1 < nk) gload(kc + 1);
       const double* as = &As[buf][0];
       const double* bs = &Bs[buf][0];
-#pragma unroll
+#pragma unroll KU
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         double fb[CG];
 #pragma unroll
@@ -474,13 +495,39 @@ __global__ void __launch_bounds__(kNT, 2) k_gemm_step(StepArgs g) {
         if (ip) {
           *dst = g.R[(i - o) * g.ldr + j];
         } else {
-          const double w = jp ? 0.0 : *dst;
+          const double w = jp ? 0.0 : g.Win[i * g.ldwin + j];
           *dst = w - acc[r][c];
         }
       }
     }
   }
-  }  // tile loop
+}
+
+template <int MODE, class C, bool A_KMAJOR, bool VEC>
+__global__ void __launch_bounds__(C::NT)
+__attribute__((amdgpu_waves_per_eu(C::NT >= 512 ? 4 : 2, C::NT >= 512 ? 4 : 2))) k_gemm_step(StepArgs g) {
+  __shared__ double As[2][C::BK * C::LA];
+  __shared__ double Bs[2][C::BK * C::LB];
+  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
+  const int64_t T8 = (g.ntiles + 7) / 8;
+  const int64_t xcd = blockIdx.x & 7, per = (int64_t)gridDim.x >> 3;
+  for (int64_t tl = (int64_t)blockIdx.x >> 3; tl < T8; tl += per) {
+    int64_t tm, tn;
+    if (!tile_of<8>(xcd * T8 + tl, TM, TN, tm, tn, g.region, g.tr0, g.tr1, g.tc0, g.tc1)) continue;
+    gemm_tile<MODE, C, A_KMAJOR, VEC>(g, tm, tn, As, Bs);
+  }
+}
+
+// Batched form: workgroup i runs every tile of problem args[i] (one small
+// matrix of a batch).
+template <int MODE, class C, bool A_KMAJOR>
+__global__ void __launch_bounds__(C::NT) k_gemm_step_batched(const StepArgs* __restrict__ args) {
+  __shared__ double As[2][C::BK * C::LA];
+  __shared__ double Bs[2][C::BK * C::LB];
+  const StepArgs g = args[blockIdx.x];
+  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
+  for (int64_t tm = 0; tm < TM; ++tm)
+    for (int64_t tn = 0; tn < TN; ++tn) gemm_tile<MODE, C, A_KMAJOR, false>(g, tm, tn, As, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,6 +562,13 @@ hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, i
   if (gx > 64) gx = 64;
   dim3 grid(gx, (unsigned)rows);
   hipLaunchKernelGGL(k_copy2d, grid, dim3(256), 0, s, S, lds, D, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 
@@ -555,10 +609,11 @@ static double step_flops(const StepArgs& g, int mode) {
   return 2.0 * g.K * cnt;
 }
 
-template <int MODE, int BM, int BN, bool AK>
+template <int MODE, int BM, int BN, bool AK, int NWM = 2, int NWN = 2>
 static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo, int qb, double* flops,
                               int slots = 0) {
-  constexpr int BK = 16;
+  using C = TileCfg<BM, BN, NWM, NWN>;
+  constexpr int BK = C::BK;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
   g.region = region;
@@ -579,9 +634,9 @@ static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo,
   const bool vec = (g.M % BM == 0) && (g.N % BN == 0) && (g.K % BK == 0) && ((g.lda & 1) == 0) &&
                    ((g.ldb & 1) == 0) && ((((uintptr_t)g.A) & 15) == 0) && ((((uintptr_t)g.B) & 15) == 0);
   if (vec)
-    hipLaunchKernelGGL((k_gemm_step<MODE, BM, BN, AK, true>), dim3((unsigned)G), dim3(kNT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, true>), dim3((unsigned)G), dim3(C::NT), 0, s, g);
   else
-    hipLaunchKernelGGL((k_gemm_step<MODE, BM, BN, AK, false>), dim3((unsigned)G), dim3(kNT), 0, s, g);
+    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, false>), dim3((unsigned)G), dim3(C::NT), 0, s, g);
   return hipGetLastError();
 }
 
@@ -592,6 +647,7 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
   g.A = P; g.lda = ldp;
   g.B = W + o * ldw; g.ldb = ldw;
   g.W = R; g.ldw = ldr;
+  g.Win = nullptr; g.ldwin = 0;
   g.R = P; g.ldr = ldp;
   g.M = b; g.N = n; g.K = b; g.o = o; g.b = b;
   return launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, flops);
@@ -608,10 +664,50 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   g.A = Ct; g.lda = ldc;
   g.B = R; g.ldb = ldr;
   g.W = W; g.ldw = ldw;
+  g.Win = W; g.ldwin = ldw;
   g.R = R; g.ldr = ldr;
   g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
-  if (schur_tile(n) == 128) return launch_step<MODE_SCHUR, 128, 128, true>(g, s, region, qo, qb, flops, slots);
+  if (schur_tile(n) == 128) {
+    static const int cfg = [] {
+      const char* e = getenv("BINV_SCHUR_CFG");
+      return e ? atoi(e) : 1;
+    }();
+    if (cfg == 1) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
+    return launch_step<MODE_SCHUR, 128, 128, true, 2, 2>(g, s, region, qo, qb, flops, slots);
+  }
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);
+}
+
+hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const dim3 g((unsigned)count);
+  if (bmax <= 32)
+    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 8, 4>), g, dim3(256), 0, s, jobs);
+  else if (bmax <= 64)
+    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 16, 4>), g, dim3(256), 0, s, jobs);
+  else
+    hipLaunchKernelGGL((k_leaf_inverse_batched<2, 16, 8>), g, dim3(512), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_save_batched(const ColJob* jobs, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_save_batched, dim3((unsigned)count), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm_step_batched<MODE_ROW, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count), dim3(256), 0,
+                     s, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, true>), dim3((unsigned)count), dim3(256),
+                     0, s, args);
+  return hipGetLastError();
 }
 
 }  // namespace binv

@@ -1,0 +1,131 @@
+"""Batched inversion of small uneven matrices against the CPU oracle (GPU).
+
+Each matrix must match the oracle's Gauss-Jordan inverse elementwise within
+64 m u kappa max|X| and have rho = ||AX - I||_F / sqrt(m) <= 1e-12 (SPD inputs
+of the batched workload), or 1e-10 for the general inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11103_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def run_batch(mats, ks=None, parts=None, graph=True, inplace=False):
+    import torch
+    from paper_2305_11103_amd import binv
+    sizes = [M.shape[0] for M in mats]
+    b = binv.Batch(sizes, ks=ks, parts=parts)
+    A = torch.from_numpy(b.pack(mats)).cuda()
+    X, info = b.invert(A, graph=graph, inplace=inplace)
+    torch.cuda.synchronize()
+    return b, b.unpack(X.cpu().numpy()), info.cpu().numpy()[: len(mats)]
+
+
+def check(A, X, bound):
+    Xo = oracle.gj_inverse(A)
+    kappa = np.linalg.cond(A)
+    m = A.shape[0]
+    assert np.max(np.abs(X - Xo)) <= 64 * m * U * kappa * np.max(np.abs(Xo))
+    assert oracle.residual_stats(A, X)["rho"] <= bound
+
+
+def test_every_tier_spd(gpu):
+    sizes = [1, 2, 5, 5, 8, 9, 16, 17, 31, 32, 33, 63, 64, 65, 100, 128, 129, 150, 200, 255, 256]
+    rng = np.random.default_rng(0)
+    mats = [wl.spd_gram(m, 100 + i) for i, m in enumerate(sizes)]
+    ks = [min(m, int(rng.integers(2, 5))) for m in sizes]
+    b, X, info = run_batch(mats, ks=ks)
+    assert np.all(info == 0)
+    for A, Xi in zip(mats, X):
+        check(A, Xi, 1e-12 if A.shape[0] > 1 else 1e-15)
+
+
+def test_explicit_partitions_and_general_matrices(gpu):
+    parts = [[3, 2], [7, 9, 4], [64, 64], [100, 28, 70], [10] * 20, [128, 128]]
+    mats = [wl.diag_dominant(sum(p), 7 + i) - 0.9 * sum(p) * np.eye(sum(p)) for i, p in enumerate(parts)]
+    b, X, info = run_batch(mats, parts=parts)
+    assert np.all(info == 0)
+    for A, Xi in zip(mats, X):
+        check(A, Xi, 1e-10)
+
+
+def test_block_restricted_pivoting_matches_blockwise_oracle(gpu):
+    """Block-diagonal inputs: off-diagonal blocks come out exactly zero, as in
+    the blockwise oracle."""
+    rng = np.random.default_rng(4)
+    parts = [[2, 3], [20, 30, 14], [90, 60]]
+    mats = []
+    for p in parts:
+        n = sum(p)
+        M = np.zeros((n, n))
+        o = 0
+        for q in p:
+            M[o:o + q, o:o + q] = rng.uniform(-1, 1, (q, q)) + q * np.eye(q)
+            o += q
+        mats.append(M)
+    b, X, info = run_batch(mats, parts=parts)
+    for A, Xi, p in zip(mats, X, parts):
+        Xb = oracle.blockwise_inverse(A, p)
+        assert np.all(Xi[Xb == 0.0] == 0.0)
+        check(A, Xi, 1e-12)
+
+
+def test_singular_member_is_reported_alone(gpu):
+    mats = [wl.spd_gram(5, 1), np.eye(6)[::-1].copy(), wl.spd_gram(40, 2), np.eye(160)[::-1].copy(),
+            wl.spd_gram(140, 3)]
+    ks = [2, 2, 3, 2, 2]
+    b, X, info = run_batch(mats, ks=ks)
+    assert info[0] == 0 and info[2] == 0 and info[4] == 0
+    assert info[1] > 0 and info[3] > 0
+    check(mats[0], X[0], 1e-12)
+    check(mats[2], X[2], 1e-12)
+    check(mats[4], X[4], 1e-12)
+
+
+def test_graph_replay_and_eager_are_bitwise_equal(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    sizes, parts = wl.batch_spec(9, count_small=300, count_large=40)
+    mats = [wl.spd_gram(m, 50 + i) for i, m in enumerate(sizes)]
+    b = binv.Batch(sizes, parts=parts)
+    A = torch.from_numpy(b.pack(mats)).cuda()
+    X0, _ = b.invert(A, graph=False)
+    X0 = X0.clone()
+    for _ in range(3):
+        X1, info = b.invert(A, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(X0, X1)
+        torch.cuda.synchronize()
+    Xs = b.unpack(X1.cpu().numpy())
+    for i in range(0, len(mats), 17):
+        check(mats[i], Xs[i], 1e-12)
+
+
+def test_inplace_batch(gpu):
+    mats = [wl.spd_gram(m, m) for m in (5, 30, 70, 200)]
+    _, X1, _ = run_batch(mats, ks=[2, 3, 4, 2])
+    _, X2, _ = run_batch(mats, ks=[2, 3, 4, 2], inplace=True)
+    for a, c in zip(X1, X2):
+        assert np.array_equal(a, c)
+
+
+def test_batched_agrees_with_single_inversion(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    m, part = 200, [70, 70, 60]
+    A = wl.spd_gram(m, 77)
+    _, X, _ = run_batch([A], parts=[part])
+    Xs = binv.invert(torch.from_numpy(A).cuda(), part=part).cpu().numpy()
+    assert np.max(np.abs(X[0] - Xs)) <= 64 * m * U * np.linalg.cond(A) * np.max(np.abs(Xs))
+
+
+def test_invalid_plans_rejected(gpu):
+    from paper_2305_11103_amd import binv
+    with pytest.raises(binv.BinvError):
+        binv.Batch([300])
+    with pytest.raises(binv.BinvError):
+        binv.Batch([5], parts=[[2, 2]])
