@@ -105,6 +105,34 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
                         void* stream, int64_t* d_info);
 
 /* ---------------------------------------------------------------------------
+ * Mixed precision: the same blockwise sweep on an FP32 working copy (row
+ * panels and Schur updates on FP32 MFMA with FP32 accumulation, every pivot
+ * block inverted in FP64), then Newton-Schulz refinement in FP64 on the
+ * original matrix, X <- X + X (I - A X), until rho = ||A X - I||_F / sqrt(n)
+ * is at most `target`.  FP64 and the device are used for the pivot blocks, the
+ * residual I - A X and its norm.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  double rho;              /* rho of the returned X, computed in FP64 on the GPU */
+  double rho_steps[8];     /* rho before refinement step 0, 1, ... */
+  int32_t refine_steps;    /* Newton-Schulz steps applied */
+  int32_t fell_back;       /* 1: refinement diverged (rho_0 >= 0.5 or rho grew),
+                              X came from the plain FP64 path instead */
+  int32_t converged;       /* 1: rho <= target */
+} binv_info;
+
+/* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
+ * is read again by the refinement.  opts: the partition (as binv_invert;
+ * flags other than BINV_F_NO_LOOKAHEAD are ignored).  target <= 0 means
+ * 1e-10; max_refine < 0 means 3 (at most 7).  The call is synchronous: it
+ * reads each residual norm back to decide the next step, and fills *info
+ * (may be NULL).  Returns BINV_E_SINGULAR for an exactly-zero pivot (in the
+ * FP32 sweep's FP64 pivot inversions, or in the fallback). */
+binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                              const binv_opts* opts, double target, int32_t max_refine, void* stream,
+                              binv_info* info);
+
+/* ---------------------------------------------------------------------------
  * Batched inversion of many small, uneven matrices.
  *
  * A plan fixes `count` matrices of orders m[i] in 1..256, packed back to back
@@ -147,7 +175,8 @@ binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, in
 #define BINV_PHASE_OTHER 3   /* copies and panel saves */
 #define BINV_PHASE_BAND 4    /* lookahead: Schur update of the next block's
                                 row and column band, on the side stream */
-#define BINV_NPHASE 5
+#define BINV_PHASE_SMALL 5   /* batched: register-resident tiers (orders <= 128) */
+#define BINV_NPHASE 6
 
 typedef struct {
   double ms[BINV_NPHASE];        /* summed device time of the timed launches */

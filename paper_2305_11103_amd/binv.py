@@ -24,10 +24,11 @@ BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
+           "binv_invert_mixed",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_last_error", "binv_version")
 BINV_F_GRAPH = 4
-PHASES = ("pivot", "row", "schur", "other", "band")
+PHASES = ("pivot", "row", "schur", "other", "band", "small")
 
 
 class BinvError(RuntimeError):
@@ -41,7 +42,12 @@ class SingularError(BinvError):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5), ("flops", ctypes.c_double * 5)]
+    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6), ("flops", ctypes.c_double * 6)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("rho_steps", ctypes.c_double * 8), ("refine_steps", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
 
 class _Opts(ctypes.Structure):
@@ -76,6 +82,9 @@ def load_library():
     lib.binv_set_timing.restype = ctypes.c_int
     lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
     lib.binv_get_timing.restype = ctypes.c_int
+    lib.binv_invert_mixed.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts),
+                                      ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(_Info)]
+    lib.binv_invert_mixed.restype = ctypes.c_int
     lib.binv_batch_create.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.POINTER(P)]
     lib.binv_batch_create.restype = ctypes.c_int
     lib.binv_batch_destroy.argtypes = [P]
@@ -215,6 +224,32 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     del keep
     _check(st)
     return X
+
+
+def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=3, ctx=None, lookahead=True):
+    """Mixed-precision inversion: FP32 blockwise sweep (FP64 pivot blocks), then
+    FP64 Newton-Schulz refinement to rho = ||AX - I||_F / sqrt(n) <= target.
+    Synchronous.  Returns (X, info dict)."""
+    import torch
+
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda or A.stride(1) != 1:
+        raise ValueError("A must be a square row-major float64 CUDA tensor")
+    n = A.shape[0]
+    X = out if out is not None else torch.empty_like(A, memory_format=torch.contiguous_format)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or default_context(dev)
+    o, keep = _opts(part, block, False, lookahead)
+    inf = _Info()
+    with torch.cuda.device(dev):
+        st = load_library().binv_invert_mixed(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
+                                              ctypes.c_void_p(X.data_ptr()), max(X.stride(0), n, 1), ctypes.byref(o),
+                                              float(target), int(max_refine), _stream_handle(torch, dev),
+                                              ctypes.byref(inf))
+    del keep
+    _check(st)
+    k = inf.refine_steps
+    return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1]), "refine_steps": k,
+               "fell_back": bool(inf.fell_back), "converged": bool(inf.converged)}
 
 
 class Batch:

@@ -52,6 +52,7 @@ binv_status upload(const std::vector<T>& h, void** d) {
 struct SweptStep {
   int64_t first = 0, count = 0;  // range in the per-step job arrays
   int bmax = 0;
+  double row_flops = 0, schur_flops = 0;  // algorithmic flops of the step's GEMMs
 };
 
 struct binv_batch {
@@ -64,6 +65,7 @@ struct binv_batch {
   std::vector<int32_t> m;
   // small tiers
   int64_t tier_first[kSmallTiers] = {0}, tier_count[kSmallTiers] = {0};
+  double tier_flops[kSmallTiers] = {0};  // 2 sum m^3 per tier
   void* d_mats = nullptr;    // SmallMat per matrix (all matrices)
   void* d_order = nullptr;   // matrix indices grouped by tier
   void* d_bounds = nullptr;  // diagonal-block boundaries
@@ -156,19 +158,39 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
   return BINV_OK;
 }
 
-// Enqueue the whole batched inversion on stream s.
-binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hipStream_t s) {
+// Enqueue the whole batched inversion on stream s.  `timed`: bracket the
+// launches with the context's phase timers (never inside a graph capture).
+binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hipStream_t s, bool timed) {
+  binv_ctx* c = b->ctx;
+  const int lvl = timed ? 0 : 1;  // level != 0 disables the timers
   // every matrix's info word starts at 0; the small tiers overwrite theirs
   BHIP(binv::launch_fill_i32(info, b->count, 0, s));
-  for (int t = 0; t < kSmallTiers; ++t)
+  for (int t = 0; t < kSmallTiers; ++t) {
+    binv::PhaseTimer tm(c, lvl, BINV_PHASE_SMALL, s);
+    if (tm.on()) tm.flops = b->tier_flops[t];
     BHIP(binv::launch_small_tier(t, A, X, (const binv::SmallMat*)b->d_mats,
                                  (const int32_t*)b->d_order + b->tier_first[t], b->tier_count[t],
                                  (const int32_t*)b->d_bounds, info, s));
+  }
   for (const SweptStep& st : b->steps) {
-    BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + st.first, st.count, st.bmax, s));
-    BHIP(binv::launch_col_save_batched((const binv::ColJob*)b->d_col + st.first, st.count, s));
-    BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, s));
-    BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, s));
+    {
+      binv::PhaseTimer tm(c, lvl, BINV_PHASE_PIVOT, s);
+      BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + st.first, st.count, st.bmax, s));
+    }
+    {
+      binv::PhaseTimer tm(c, lvl, BINV_PHASE_OTHER, s);
+      BHIP(binv::launch_col_save_batched((const binv::ColJob*)b->d_col + st.first, st.count, s));
+    }
+    {
+      binv::PhaseTimer tm(c, lvl, BINV_PHASE_ROW, s);
+      if (tm.on()) tm.flops = st.row_flops;
+      BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, s));
+    }
+    {
+      binv::PhaseTimer tm(c, lvl, BINV_PHASE_SCHUR, s);
+      if (tm.on()) tm.flops = st.schur_flops;
+      BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, s));
+    }
   }
   return BINV_OK;
 }
@@ -255,6 +277,7 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
       int t = 0;
       while (mi > binv::small_tier_limit(t)) ++t;
       tiers[t].push_back((int32_t)i);
+      b->tier_flops[t] += 2.0 * mi * (double)mi * mi;
     } else {
       b->swept.push_back((int32_t)i);
       maxsteps = std::max(maxsteps, (int)fin.size());
@@ -288,7 +311,11 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
       const int nb = b->bnd_index[i + 1] - bi - 1;
       if (s < nb) {
         ++st.count;
-        st.bmax = std::max(st.bmax, b->bounds_host[bi + s + 1] - b->bounds_host[bi + s]);
+        const int bs = b->bounds_host[bi + s + 1] - b->bounds_host[bi + s];
+        const double mi = b->m[i];
+        st.bmax = std::max(st.bmax, bs);
+        st.row_flops += 2.0 * bs * (double)bs * (mi - bs);
+        st.schur_flops += 2.0 * bs * (mi - bs) * mi;
       }
     }
     first += st.count;
@@ -349,7 +376,7 @@ binv_status binv_invert_batched(binv_batch* b, const double* A, double* X, int32
     if (!b->exec) {
       if (!b->cap) BHIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
       BHIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-      binv_status st = enqueue(b, A, X, d_info, b->cap);
+      binv_status st = enqueue(b, A, X, d_info, b->cap, false);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(b->cap, &g);
       if (st != BINV_OK) {
@@ -362,7 +389,7 @@ binv_status binv_invert_batched(binv_batch* b, const double* A, double* X, int32
     }
     BHIP(hipGraphLaunch(b->exec, s));
   } else {
-    binv_status st = enqueue(b, A, X, d_info, s);
+    binv_status st = enqueue(b, A, X, d_info, s, true);
     if (st != BINV_OK) return st;
   }
   if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));

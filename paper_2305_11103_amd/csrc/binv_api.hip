@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -40,96 +41,13 @@ namespace {
       return fail(BINV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
   } while (0)
 
-// A growable device buffer.
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  binv_status ensure(size_t want) {
-    if (want <= bytes) return BINV_OK;
-    if (p) {
-      hipError_t e = hipFree(p);
-      p = nullptr;
-      bytes = 0;
-      if (e != hipSuccess) return fail(BINV_E_HIP, std::string("hipFree: ") + hipGetErrorString(e));
-    }
-    if (hipMalloc(&p, want) != hipSuccess) {
-      p = nullptr;
-      return fail(BINV_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
-    }
-    bytes = want;
-    return BINV_OK;
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-};
-
-// Workspace for one recursion level of the block sweep (two sets of panels:
-// under lookahead the next block's panels are formed while the current ones
-// are still being read).
-struct Level {
-  DevBuf ct[2];  // old column panel, k-major: b x n
-  DevBuf r[2];   // row panel: b x n
-  DevBuf p[2];   // pivot inverse: b x b
-};
-
 }  // namespace
 
-struct binv_ctx {
-  int device = 0;
-  int ncu = 256;  // compute units of the device
-  Level lv[2];
-  DevBuf info;  // scratch info word when the caller passes none
-  // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few
-  // CUs) while the next pivot inversion runs on `side` (masked to the rest)
-  hipStream_t side = nullptr, gemm = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
-  // optional per-phase event timing
-  uint32_t timing_mask = 0;
-  std::vector<hipEvent_t> ev_free;
-  struct Pending { int phase; hipEvent_t a, b; double flops; };
-  std::vector<Pending> pending;
-};
+using binv::DevBuf;
+using binv::Level;
+using binv::PhaseTimer;
 
 namespace {
-
-// Brackets one top-level launch with events when its phase is being timed.
-struct PhaseTimer {
-  binv_ctx* c;
-  int phase;
-  hipStream_t s;
-  hipEvent_t a = nullptr, b = nullptr;
-  double flops = 0.0;
-  bool on() const { return a && b; }
-  double* fl() { return on() ? &flops : nullptr; }
-  PhaseTimer(binv_ctx* c_, int level, int phase_, hipStream_t s_) : c(c_), phase(phase_), s(s_) {
-    if (level != 0 || !(c->timing_mask & (1u << phase))) return;
-    a = take();
-    b = take();
-    if (a && b) (void)hipEventRecord(a, s);
-  }
-  hipEvent_t take() {
-    if (!c->ev_free.empty()) {
-      hipEvent_t e = c->ev_free.back();
-      c->ev_free.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-  ~PhaseTimer() {
-    if (a && b) {
-      (void)hipEventRecord(b, s);
-      c->pending.push_back({phase, a, b, flops});
-    } else {
-      if (a) c->ev_free.push_back(a);
-      if (b) c->ev_free.push_back(b);
-    }
-  }
-};
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
                   hipStream_t s, long long* info, int64_t row0, bool lookahead);
@@ -308,6 +226,9 @@ binv_status binv_destroy(binv_ctx* ctx) {
   for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_gemm})
     if (e) (void)hipEventDestroy(e);
   ctx->info.release();
+  for (binv::DevBuf* d : {&ctx->mx_w32, &ctx->mx_ct32, &ctx->mx_r32, &ctx->mx_p32, &ctx->mx_p64a, &ctx->mx_p64b,
+                          &ctx->mx_res, &ctx->mx_xn, &ctx->mx_part})
+    d->release();
   for (auto& p : ctx->pending) {
     (void)hipEventSynchronize(p.b);
     (void)hipEventDestroy(p.a);
@@ -343,6 +264,194 @@ binv_status binv_get_timing(binv_ctx* ctx, binv_timing* out) {
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+binv_status parse_partition(int64_t n, const binv_opts* opts, std::vector<int32_t>& part) {
+  part.clear();
+  if (opts && opts->part) {
+    if (opts->k <= 0) return fail(BINV_E_INVALID, "k must be positive when part is given");
+    int64_t sum = 0;
+    for (int32_t i = 0; i < opts->k; ++i) {
+      if (opts->part[i] <= 0) return fail(BINV_E_INVALID, "non-positive block order in part");
+      sum += opts->part[i];
+      part.push_back(opts->part[i]);
+    }
+    if (sum != n) return fail(BINV_E_INVALID, "block orders do not sum to n");
+  } else {
+    if (opts && opts->block < 0) return fail(BINV_E_INVALID, "negative block order");
+    int32_t blk = (opts && opts->block > 0) ? opts->block : 512;
+    for (int64_t off = 0; off < n; off += blk) part.push_back((int32_t)std::min<int64_t>(blk, n - off));
+  }
+  for (int32_t b : part)
+    if (b > binv::kLeafMax * binv::kSubBlock) return fail(BINV_E_INVALID, "diagonal block larger than 8192");
+  return BINV_OK;
+}
+
+binv_status read_info(long long* info, hipStream_t s, long long* h) {
+  HIP_TRY(hipMemcpyAsync(h, info, sizeof(*h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BINV_OK;
+}
+
+// rho = ||I - A X||_F / sqrt(n) with the residual left in Res (FP64 GEMM).
+binv_status residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
+                          double* Res, hipStream_t s, double* rho) {
+  HIP_TRY(binv::launch_gemm_f64(binv::kModeResid, A, lda, X, ldx, nullptr, 0, Res, n, n, s, nullptr));
+  double* part = (double*)c->mx_part.p;
+  HIP_TRY(binv::launch_sumsq(Res, n, n, part, part + binv::kSumPartsHost, s));
+  double h = 0.0;
+  HIP_TRY(hipMemcpyAsync(&h, part + binv::kSumPartsHost, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *rho = std::sqrt(h / (double)n);
+  return BINV_OK;
+}
+
+// The blockwise sweep on an FP32 copy of A (pivot blocks inverted in FP64);
+// leaves X = FP64(result).
+binv_status sweep_f32(binv_ctx* c, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                      const std::vector<int32_t>& part, hipStream_t s, long long* info) {
+  int bmax = 0;
+  for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  binv_status st;
+  const size_t nn = (size_t)n * (size_t)n;
+  if ((st = c->mx_w32.ensure(sizeof(float) * nn)) != BINV_OK) return st;
+  if ((st = c->mx_ct32.ensure(sizeof(float) * (size_t)bmax * n)) != BINV_OK) return st;
+  if ((st = c->mx_r32.ensure(sizeof(float) * (size_t)bmax * n)) != BINV_OK) return st;
+  if ((st = c->mx_p32.ensure(sizeof(float) * (size_t)bmax * bmax)) != BINV_OK) return st;
+  if ((st = c->mx_p64a.ensure(sizeof(double) * (size_t)bmax * bmax)) != BINV_OK) return st;
+  if ((st = c->mx_p64b.ensure(sizeof(double) * (size_t)bmax * bmax)) != BINV_OK) return st;
+  float* W = (float*)c->mx_w32.p;
+  float* Ct = (float*)c->mx_ct32.p;
+  float* R = (float*)c->mx_r32.p;
+  float* P32 = (float*)c->mx_p32.p;
+  double* Pa = (double*)c->mx_p64a.p;
+  double* Pb = (double*)c->mx_p64b.p;
+  HIP_TRY(binv::launch_f64_to_f32(A, lda, W, n, n, n, s));
+  int64_t o = 0;
+  for (int32_t b : part) {
+    HIP_TRY(binv::launch_f32_to_f64(W + o * n + o, n, Pa, b, b, b, s));
+    const double* Pinv = Pb;
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_PIVOT, s);
+      if (b <= binv::kLeafMax) {
+        HIP_TRY(binv::launch_leaf_inverse(Pa, b, Pb, b, b, o, info, s));
+      } else {
+        std::vector<int32_t> sub;
+        for (int off = 0; off < b; off += binv::kSubBlock) sub.push_back(std::min(binv::kSubBlock, b - off));
+        if ((st = sweep(c, 1, b, Pa, b, sub, s, info, o, false)) != BINV_OK) return st;
+        Pinv = Pa;
+      }
+    }
+    HIP_TRY(binv::launch_f64_to_f32(Pinv, b, P32, b, b, b, s));
+    HIP_TRY(binv::launch_col_save_f32(W, n, n, o, b, Ct, n, s));
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_ROW, s);
+      if (t.on()) t.flops = 2.0 * b * (double)b * (double)(n - b);
+      HIP_TRY(binv::launch_row_panel_f32(P32, b, W, n, n, o, b, R, n, s));
+    }
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_SCHUR, s);
+      if (t.on()) t.flops = 2.0 * b * (double)(n - b) * (double)n;
+      HIP_TRY(binv::launch_schur_f32(Ct, n, R, n, W, n, n, o, b, s));
+    }
+    o += b;
+  }
+  HIP_TRY(binv::launch_f32_to_f64(W, n, X, ldx, n, n, s));
+  return BINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                              const binv_opts* opts, double target, int32_t max_refine, void* stream,
+                              binv_info* info_out) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (n > 0 && (!A || !X)) return fail(BINV_E_INVALID, "A or X is NULL");
+  if (n > 0 && (lda < n || ldx < n)) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  if (n > 0) {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + (n - 1) * lda + n);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + (n - 1) * ldx + n);
+    if (a0 < x1 && x0 < a1) return fail(BINV_E_INVALID, "mixed precision needs X separate from A");
+  }
+  if (target <= 0) target = 1e-10;
+  if (max_refine < 0) max_refine = 3;
+  if (max_refine > 7) max_refine = 7;
+  binv_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  std::vector<int32_t> part;
+  binv_status st = parse_partition(n, opts, part);
+  if (st != BINV_OK) return st;
+  if (n == 0) {
+    inf.converged = 1;
+    if (info_out) *info_out = inf;
+    return BINV_OK;
+  }
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nn = (size_t)n * (size_t)n;
+  long long hinfo = 0;
+  double rho = 0.0;
+  double* Res = nullptr;
+  double* Xn = nullptr;
+  long long* dinfo = nullptr;
+  if ((st = ctx->info.ensure(sizeof(long long))) != BINV_OK) goto out;
+  dinfo = (long long*)ctx->info.p;
+  if ((st = ctx->mx_res.ensure(sizeof(double) * nn)) != BINV_OK) goto out;
+  if ((st = ctx->mx_xn.ensure(sizeof(double) * nn)) != BINV_OK) goto out;
+  if ((st = ctx->mx_part.ensure(sizeof(double) * (binv::kSumPartsHost + 1))) != BINV_OK) goto out;
+  Res = (double*)ctx->mx_res.p;
+  Xn = (double*)ctx->mx_xn.p;
+  {
+    hipError_t e = binv::launch_zero_info(dinfo, s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+  }
+  if ((st = sweep_f32(ctx, n, A, lda, X, ldx, part, s, dinfo)) != BINV_OK) goto out;
+  if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
+  if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
+  for (int k = 0;; ++k) {
+    if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+    if (k < 8) inf.rho_steps[k] = rho;
+    if (rho <= target) { inf.converged = 1; break; }
+    const bool diverging = !(rho < 0.5) || (k > 0 && !(rho < inf.rho_steps[k - 1]));
+    if (diverging) {
+      // fall back to the plain FP64 sweep
+      inf.fell_back = 1;
+      hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD)))) != BINV_OK)
+        goto out;
+      if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
+      if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
+      if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+      inf.converged = rho <= target;
+      break;
+    }
+    if (k >= max_refine) break;
+    // X <- X + X (I - A X)
+    {
+      PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
+      hipError_t e = binv::launch_gemm_f64(binv::kModeAdd, X, ldx, Res, n, X, ldx, Xn, n, n, s, nullptr);
+      if (e == hipSuccess) e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+    }
+    inf.refine_steps = k + 1;
+  }
+  inf.rho = rho;
+out:
+  if (info_out) *info_out = inf;
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
 binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
                         const binv_opts* opts, void* stream, int64_t* d_info) {
   if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
@@ -360,22 +469,10 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
   }
   std::vector<int32_t> part;
   uint32_t flags = opts ? opts->flags : 0u;
-  if (opts && opts->part) {
-    if (opts->k <= 0) return fail(BINV_E_INVALID, "k must be positive when part is given");
-    int64_t sum = 0;
-    for (int32_t i = 0; i < opts->k; ++i) {
-      if (opts->part[i] <= 0) return fail(BINV_E_INVALID, "non-positive block order in part");
-      sum += opts->part[i];
-      part.push_back(opts->part[i]);
-    }
-    if (sum != n) return fail(BINV_E_INVALID, "block orders do not sum to n");
-  } else {
-    int32_t blk = (opts && opts->block > 0) ? opts->block : 512;
-    if (opts && opts->block < 0) return fail(BINV_E_INVALID, "negative block order");
-    for (int64_t off = 0; off < n; off += blk) part.push_back((int32_t)std::min<int64_t>(blk, n - off));
+  {
+    binv_status pst = parse_partition(n, opts, part);
+    if (pst != BINV_OK) return pst;
   }
-  for (int32_t b : part)
-    if (b > binv::kLeafMax * binv::kSubBlock) return fail(BINV_E_INVALID, "diagonal block larger than 8192");
 
   int prev = 0;
   HIP_TRY(hipGetDevice(&prev));

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/binv.h"
 
@@ -86,6 +87,25 @@ hipError_t launch_col_save_batched(const ColJob* jobs, int64_t count, hipStream_
 hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s);
 hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s);
 
+hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
+                           int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);
+constexpr int kModeResid = 2;  // C = I - A B
+constexpr int kModeAdd = 3;    // C = Cin + A B
+
+// mixed.hip
+hipError_t launch_f64_to_f32(const double* S, int64_t lds, float* D, int64_t ldd, int64_t rows, int64_t cols,
+                             hipStream_t s);
+hipError_t launch_f32_to_f64(const float* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
+                             hipStream_t s);
+hipError_t launch_col_save_f32(const float* W, int64_t ldw, int64_t n, int64_t o, int b, float* Ct, int64_t ldc,
+                               hipStream_t s);
+hipError_t launch_row_panel_f32(const float* P, int64_t ldp, const float* W, int64_t ldw, int64_t n, int64_t o, int b,
+                                float* R, int64_t ldr, hipStream_t s);
+hipError_t launch_schur_f32(const float* Ct, int64_t ldc, const float* R, int64_t ldr, float* W, int64_t ldw, int64_t n,
+                            int64_t o, int b, hipStream_t s);
+hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t n, double* part, double* out, hipStream_t s);
+constexpr int kSumPartsHost = 1024;
+
 // batched.hip
 hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                              int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s);
@@ -93,6 +113,104 @@ int small_tier_limit(int tier);
 
 // binv_api.hip: records the thread-local message returned by binv_last_error
 void set_error(const std::string& msg);
+
+// A growable device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  binv_status ensure(size_t want) {
+    if (want <= bytes) return BINV_OK;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) {
+        binv::set_error(std::string("hipFree: ") + hipGetErrorString(e));
+        return BINV_E_HIP;
+      }
+    }
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      binv::set_error("hipMalloc of " + std::to_string(want) + " bytes failed");
+      return BINV_E_NOMEM;
+    }
+    bytes = want;
+    return BINV_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Workspace for one recursion level of the block sweep (two sets of panels:
+// under lookahead the next block's panels are formed while the current ones
+// are still being read).
+struct Level {
+  DevBuf ct[2];  // old column panel, k-major: b x n
+  DevBuf r[2];   // row panel: b x n
+  DevBuf p[2];   // pivot inverse: b x b
+};
+
+}  // namespace binv
+
+// The library context (opaque to callers; see include/binv.h).
+struct binv_ctx {
+  int device = 0;
+  int ncu = 256;  // compute units of the device
+  binv::Level lv[2];
+  binv::DevBuf info;  // scratch info word when the caller passes none
+  // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few
+  // CUs) while the next pivot inversion runs on `side` (masked to the rest)
+  hipStream_t side = nullptr, gemm = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
+  // mixed precision workspace
+  binv::DevBuf mx_w32, mx_ct32, mx_r32, mx_p32, mx_p64a, mx_p64b, mx_res, mx_xn, mx_part;
+  // optional per-phase event timing
+  uint32_t timing_mask = 0;
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { int phase; hipEvent_t a, b; double flops; };
+  std::vector<Pending> pending;
+};
+
+namespace binv {
+
+// Brackets one top-level launch with events when its phase is being timed.
+struct PhaseTimer {
+  binv_ctx* c;
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  double flops = 0.0;
+  bool on() const { return a && b; }
+  double* fl() { return on() ? &flops : nullptr; }
+  PhaseTimer(binv_ctx* c_, int level, int phase_, hipStream_t s_) : c(c_), phase(phase_), s(s_) {
+    if (level != 0 || !(c->timing_mask & (1u << phase))) return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    if (!c->ev_free.empty()) {
+      hipEvent_t e = c->ev_free.back();
+      c->ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~PhaseTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      c->pending.push_back({phase, a, b, flops});
+    } else {
+      if (a) c->ev_free.push_back(a);
+      if (b) c->ev_free.push_back(b);
+    }
+  }
+};
 
 constexpr int kLeafMax = 128;   // largest pivot block the register leaf kernel holds
 constexpr int kSubBlock = 64;   // sub-block order of the nested sweep of a larger pivot block

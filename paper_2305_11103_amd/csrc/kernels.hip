@@ -264,7 +264,9 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t* p, int64_t n, int32_t
 // ---------------------------------------------------------------------------
 // GEMM step kernel.
 // ---------------------------------------------------------------------------
-enum { MODE_ROW = 0, MODE_SCHUR = 1 };
+enum { MODE_ROW = 0, MODE_SCHUR = 1, MODE_RESID = 2, MODE_ADD = 3 };
+// MODE_RESID: W = I - A B (refinement residual); MODE_ADD: W = Win + A B
+// (refinement correction).  Both read A m-major (row-major A) and B k-major.
 
 typedef double dbl;
 
@@ -348,7 +350,8 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
 
   // Does this tile need the contraction at all?
   bool need = true;
-  if (MODE == MODE_SCHUR) {
+  if (MODE == MODE_RESID || MODE == MODE_ADD) {
+  } else if (MODE == MODE_SCHUR) {
     if (m0 >= o && m0 + BM <= o + b) need = false;  // rows inside block p: copy of R
   } else {
     if (n0 >= o && n0 + BN <= o + b) need = false;  // columns inside block p: copy of P
@@ -486,7 +489,11 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
       const int64_t j = n0 + wn * WN + c * 16 + ec;
       if (j >= g.N) continue;
       const bool jp = (j >= o && j < o + b);
-      if (MODE == MODE_ROW) {
+      if (MODE == MODE_RESID) {
+        g.W[i * g.ldw + j] = (i == j ? 1.0 : 0.0) - acc[r][c];
+      } else if (MODE == MODE_ADD) {
+        g.W[i * g.ldw + j] = g.Win[i * g.ldwin + j] + acc[r][c];
+      } else if (MODE == MODE_ROW) {
         // R[i][j] = P[i][j - o] for the block's own columns, else (P W_p)[i][j]
         g.W[i * g.ldw + j] = jp ? g.R[i * g.ldr + (j - o)] : acc[r][c];
       } else {
@@ -676,6 +683,21 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
     return launch_step<MODE_SCHUR, 128, 128, true, 2, 2>(g, s, region, qo, qb, flops, slots);
   }
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);
+}
+
+// Plain FP64 products for the refinement: C = I - A B (resid) or C = Cin + A B,
+// all n x n row-major.
+hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
+                           int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops) {
+  StepArgs g;
+  g.A = A; g.lda = lda;
+  g.B = B; g.ldb = ldb;
+  g.W = C; g.ldw = ldc;
+  g.Win = Cin; g.ldwin = ldcin;
+  g.R = nullptr; g.ldr = 0;
+  g.M = n; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
+  if (mode == MODE_RESID) return launch_step<MODE_RESID, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
+  return launch_step<MODE_ADD, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
 }
 
 hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s) {

@@ -1,0 +1,59 @@
+"""Mixed-precision inversion (FP32 sweep, FP64 pivots, FP64 Newton-Schulz)
+against the CPU oracle (GPU).
+
+Gate: the library's own FP64 rho must be <= target (1e-10), and the oracle's
+compensated rho of the returned X must agree with it and meet
+max(1e-10, 2 rho_oracle) (the oracle's own inverse may not reach 1e-10 at
+high condition numbers)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11103_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def run(A_np, **kw):
+    import torch
+    from paper_2305_11103_amd import binv
+    A = torch.from_numpy(A_np).cuda()
+    X, info = binv.invert_mixed(A, **kw)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("n,cond,blk", [(512, 1e2, 128), (768, 1e4, 256), (1024, 1e3, 512)])
+def test_mixed_converges_to_target(gpu, n, cond, blk):
+    A = wl.general_haar(n, 31 + n, cond)
+    X, info = run(A, block=blk)
+    Xo = oracle.gj_inverse(A)
+    rho_o = oracle.residual_stats(A, Xo)["rho"]
+    rho = oracle.residual_stats(A, X)["rho"]
+    assert info["converged"] and not info["fell_back"]
+    assert info["refine_steps"] >= 1
+    assert rho <= max(1e-10, 2 * rho_o)
+    assert abs(rho - info["rho"]) <= 0.5 * max(rho, info["rho"]) + 1e-16
+    # Newton-Schulz squares the residual (up to rounding) at each step
+    r = info["rho_steps"]
+    for a, b in zip(r, r[1:]):
+        assert b <= 10 * np.sqrt(n) * a * a + 1e-13
+    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    assert err <= 1e-14 * cond * 100
+
+
+def test_mixed_ill_conditioned_falls_back_or_converges(gpu):
+    n = 512
+    A = wl.general_haar(n, 5, 1e7)
+    X, info = run(A, block=128, max_refine=3)
+    rho = oracle.residual_stats(A, X)["rho"]
+    rho_o = oracle.residual_stats(A, oracle.gj_inverse(A))["rho"]
+    assert info["converged"] or info["fell_back"]
+    assert rho <= max(1e-10, 4 * rho_o)
+
+
+def test_mixed_singular(gpu):
+    from paper_2305_11103_amd import binv
+    A = np.eye(64)[::-1].copy()
+    with pytest.raises(binv.SingularError):
+        run(A, block=32)
