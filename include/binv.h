@@ -53,12 +53,21 @@ typedef enum {
   BINV_E_INVALID = 1,   /* bad argument (sizes, partition, pointers) */
   BINV_E_SINGULAR = 2,  /* an exactly-zero pivot inside a diagonal block */
   BINV_E_NOMEM = 3,     /* device allocation failed */
-  BINV_E_HIP = 5        /* a HIP runtime call failed */
+  BINV_E_HIP = 5,       /* a HIP runtime call failed */
+  BINV_E_BUSY = 6,      /* binv_poll: the request is not finished yet */
+  BINV_E_NOTFOUND = 7   /* binv_poll: unknown (or already collected) ticket */
 } binv_status;
+
+typedef enum {
+  BINV_PREC_FP64 = 0,       /* plain FP64 blockwise inversion */
+  BINV_PREC_MIXED_F32 = 1   /* FP32 sweep + FP64 Newton-Schulz (binv_invert_mixed) */
+} binv_prec;
 
 /* Flags for binv_opts.flags. */
 #define BINV_F_SYNC 1u    /* synchronize the stream before returning and report
                              BINV_E_SINGULAR from the device-side info word */
+#define BINV_F_REFINE_FROM_FP64 8u /* binv_invert_mixed: start the refinement from
+                             the plain FP64 sweep instead of the FP32 one */
 #define BINV_F_GRAPH 4u  /* batched calls: capture the whole launch sequence in
                              a HIP graph on first use and replay it (re-captured
                              when the A, X or info pointers change) */
@@ -114,20 +123,27 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
  * --------------------------------------------------------------------------- */
 typedef struct {
   double rho;              /* rho of the returned X, computed in FP64 on the GPU */
-  double rho_steps[8];     /* rho before refinement step 0, 1, ... */
+  double rho_steps[8];     /* rho of each successive iterate: the FP32 sweep's
+                              (if it fell back), the starting sweep's, then
+                              after each Newton-Schulz step */
   int32_t refine_steps;    /* Newton-Schulz steps applied */
-  int32_t fell_back;       /* 1: refinement diverged (rho_0 >= 0.5 or rho grew),
-                              X came from the plain FP64 path instead */
+  int32_t fell_back;       /* 1: the FP32 sweep's rho was >= 0.5 (Newton-Schulz
+                              would not converge), so the FP64 sweep was used
+                              as the starting point */
   int32_t converged;       /* 1: rho <= target */
 } binv_info;
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
- * is read again by the refinement.  opts: the partition (as binv_invert;
- * flags other than BINV_F_NO_LOOKAHEAD are ignored).  target <= 0 means
- * 1e-10; max_refine < 0 means 3 (at most 7).  The call is synchronous: it
- * reads each residual norm back to decide the next step, and fills *info
- * (may be NULL).  Returns BINV_E_SINGULAR for an exactly-zero pivot (in the
- * FP32 sweep's FP64 pivot inversions, or in the fallback). */
+ * is read again by the refinement.  opts: the partition (as binv_invert) and
+ * the flags BINV_F_NO_LOOKAHEAD, BINV_F_REFINE_FROM_FP64.  Refinement stops
+ * once rho <= target (target <= 0 means 1e-10), after max_refine steps
+ * (< 0 means 5, at most 6), or when rho stops decreasing.  Because the sweep
+ * never pivots across diagonal blocks, its error can grow on nonsymmetric
+ * inputs; the refinement repairs that whenever the start has rho < 0.5.
+ * The call is synchronous: it reads each residual norm back to decide the
+ * next step, and fills *info (may be NULL).  Returns BINV_E_SINGULAR for an
+ * exactly-zero pivot; a result that misses the target is not an error (see
+ * info->converged). */
 binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
                               const binv_opts* opts, double target, int32_t max_refine, void* stream,
                               binv_info* info);
@@ -166,6 +182,43 @@ binv_status binv_batch_query(const binv_batch* plan, int64_t* count, int64_t* to
  * undefined.  flags: BINV_F_GRAPH, BINV_F_SYNC.  Stream-ordered on `stream`. */
 binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, int32_t* d_info, uint32_t flags,
                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of inversion requests of mixed orders.
+ *
+ * binv_submit copies A (a host or device pointer; the caller may reuse it at
+ * once) into server-owned staging memory and returns a ticket; it never
+ * blocks on the device.  A scheduler thread admits queued requests in FIFO
+ * order while the server's HBM budget (bytes of device memory held for
+ * admitted, not yet collected requests, including their working panels) and
+ * in-flight limit allow.  Admitted requests of order <= 128 are grouped into
+ * shared batched launches (one Gauss-Jordan pass each, pivoting over the
+ * whole matrix); larger ones are inverted by the blockwise sweep on worker
+ * threads with their own streams, so their work overlaps on the device.
+ * Requests tagged BINV_PREC_MIXED_F32 of order > 128 use binv_invert_mixed
+ * with the given residual target; small ones are always FP64.
+ * binv_poll returns BINV_E_BUSY until the request is done; then it copies X
+ * (n x n row-major, host or device pointer, may be NULL), fills *info and
+ * *times (either may be NULL), releases the request's device memory and
+ * forgets the ticket.  A finished request keeps its memory until it is
+ * polled.  Errors: BINV_E_NOMEM from binv_submit when the request alone
+ * exceeds the budget; BINV_E_SINGULAR (and the other codes) from binv_poll
+ * for a request that failed.
+ * --------------------------------------------------------------------------- */
+typedef struct binv_server binv_server;
+
+typedef struct {
+  double queue_ms;   /* submit -> admission */
+  double total_ms;   /* submit -> result ready (latency) */
+} binv_request_times;
+
+binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_inflight, binv_server** server);
+binv_status binv_submit(binv_server* server, int64_t n, const double* A, int a_is_device, int32_t prec,
+                        double target, uint64_t* ticket);
+binv_status binv_poll(binv_server* server, uint64_t ticket, double* X, int x_is_device, binv_info* info,
+                      binv_request_times* times);
+/* Stops the scheduler, lets running requests finish, frees everything. */
+binv_status binv_server_destroy(binv_server* server);
 
 /* Per-phase kernel timing, for measurement.  Phases: */
 #define BINV_PHASE_PIVOT 0   /* pivot-block inversion (leaf kernels, sub-sweeps) */

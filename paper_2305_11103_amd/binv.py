@@ -28,6 +28,7 @@ EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "bin
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_last_error", "binv_version")
 BINV_F_GRAPH = 4
+BINV_F_REFINE_FROM_FP64 = 8
 PHASES = ("pivot", "row", "schur", "other", "band", "small")
 
 
@@ -226,7 +227,8 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     return X
 
 
-def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=3, ctx=None, lookahead=True):
+def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=True,
+                 from_fp64=False):
     """Mixed-precision inversion: FP32 blockwise sweep (FP64 pivot blocks), then
     FP64 Newton-Schulz refinement to rho = ||AX - I||_F / sqrt(n) <= target.
     Synchronous.  Returns (X, info dict)."""
@@ -239,6 +241,8 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=3,
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
     ctx = ctx or default_context(dev)
     o, keep = _opts(part, block, False, lookahead)
+    if from_fp64:
+        o.flags |= BINV_F_REFINE_FROM_FP64
     inf = _Info()
     with torch.cuda.device(dev):
         st = load_library().binv_invert_mixed(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
@@ -248,7 +252,7 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=3,
     del keep
     _check(st)
     k = inf.refine_steps
-    return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1]), "refine_steps": k,
+    return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1 + inf.fell_back]), "refine_steps": k,
                "fell_back": bool(inf.fell_back), "converged": bool(inf.converged)}
 
 

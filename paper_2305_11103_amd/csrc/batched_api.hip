@@ -5,7 +5,8 @@
 // register-resident tiers (k_small_inverse: one pass, pivoting restricted to
 // each diagonal block); orders 129..256 are swept block by block with batched
 // step kernels (one workgroup per matrix: pivot leaf, column-panel save, row
-// panel, Schur update), the same Eq. (a) step as the single-matrix path.  All
+// panel, Schur update with the column panel saved in-kernel), the same Eq. (a)
+// step as the single-matrix path.  All
 // job tables live on the device, so a run is a fixed sequence of launches that
 // is captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
@@ -53,6 +54,7 @@ struct SweptStep {
   int64_t first = 0, count = 0;  // range in the per-step job arrays
   int bmax = 0;
   double row_flops = 0, schur_flops = 0;  // algorithmic flops of the step's GEMMs
+  double leaf_flops = 0;                  // 2 b^3 per pivot block
 };
 
 struct binv_batch {
@@ -80,7 +82,6 @@ struct binv_batch {
   void* bound_X = nullptr;
   void* bound_info = nullptr;
   void* d_leaf = nullptr;
-  void* d_col = nullptr;
   void* d_row = nullptr;
   void* d_schur = nullptr;
   // graph of the whole run for the current binding
@@ -94,7 +95,7 @@ struct binv_batch {
 namespace {
 
 void free_bindings(binv_batch* b) {
-  for (void** p : {&b->d_leaf, &b->d_col, &b->d_row, &b->d_schur}) {
+  for (void** p : {&b->d_leaf, &b->d_row, &b->d_schur}) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
@@ -111,7 +112,6 @@ void free_bindings(binv_batch* b) {
 binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
   free_bindings(b);
   std::vector<binv::LeafJob> leaf;
-  std::vector<binv::ColJob> col;
   std::vector<binv::StepArgs> row, schur;
   double* ws = (double*)b->d_ws;
   for (size_t s = 0; s < b->steps.size(); ++s) {
@@ -132,9 +132,6 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
       lj.A = Win + (int64_t)o * mi + o; lj.lda = mi; lj.P = P; lj.ldp = bs; lj.b = bs; lj.row0 = o;
       lj.info = info + i;
       leaf.push_back(lj);
-      binv::ColJob cj;
-      cj.W = Win; cj.ldw = mi; cj.n = mi; cj.o = o; cj.b = bs; cj.Ct = Ct; cj.ldc = mi;
-      col.push_back(cj);
       binv::StepArgs ra;
       std::memset(&ra, 0, sizeof(ra));
       ra.A = P; ra.lda = bs; ra.B = Win + (int64_t)o * mi; ra.ldb = mi; ra.W = R; ra.ldw = mi;
@@ -142,14 +139,14 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
       row.push_back(ra);
       binv::StepArgs sa;
       std::memset(&sa, 0, sizeof(sa));
-      sa.A = Ct; sa.lda = mi; sa.B = R; sa.ldb = mi; sa.W = Wout; sa.ldw = mi; sa.Win = Win; sa.ldwin = mi;
+      // the Schur kernel copies the old column panel into Ct (row-major, ld = b) first
+      sa.A = Ct; sa.lda = bs; sa.B = R; sa.ldb = mi; sa.W = Wout; sa.ldw = mi; sa.Win = Win; sa.ldwin = mi;
       sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs;
       schur.push_back(sa);
     }
   }
   binv_status st;
   if ((st = upload(leaf, &b->d_leaf)) != BINV_OK) return st;
-  if ((st = upload(col, &b->d_col)) != BINV_OK) return st;
   if ((st = upload(row, &b->d_row)) != BINV_OK) return st;
   if ((st = upload(schur, &b->d_schur)) != BINV_OK) return st;
   b->bound_A = A;
@@ -175,11 +172,8 @@ binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hi
   for (const SweptStep& st : b->steps) {
     {
       binv::PhaseTimer tm(c, lvl, BINV_PHASE_PIVOT, s);
+      if (tm.on()) tm.flops = st.leaf_flops;
       BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + st.first, st.count, st.bmax, s));
-    }
-    {
-      binv::PhaseTimer tm(c, lvl, BINV_PHASE_OTHER, s);
-      BHIP(binv::launch_col_save_batched((const binv::ColJob*)b->d_col + st.first, st.count, s));
     }
     {
       binv::PhaseTimer tm(c, lvl, BINV_PHASE_ROW, s);
@@ -315,6 +309,7 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
         const double mi = b->m[i];
         st.bmax = std::max(st.bmax, bs);
         st.row_flops += 2.0 * bs * (double)bs * (mi - bs);
+        st.leaf_flops += 2.0 * bs * (double)bs * bs;
         st.schur_flops += 2.0 * bs * (mi - bs) * mi;
       }
     }

@@ -381,8 +381,8 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     if (a0 < x1 && x0 < a1) return fail(BINV_E_INVALID, "mixed precision needs X separate from A");
   }
   if (target <= 0) target = 1e-10;
-  if (max_refine < 0) max_refine = 3;
-  if (max_refine > 7) max_refine = 7;
+  if (max_refine < 0) max_refine = 5;
+  if (max_refine > 6) max_refine = 6;
   binv_info inf;
   std::memset(&inf, 0, sizeof(inf));
   std::vector<int32_t> part;
@@ -414,36 +414,48 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     hipError_t e = binv::launch_zero_info(dinfo, s);
     if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
   }
-  if ((st = sweep_f32(ctx, n, A, lda, X, ldx, part, s, dinfo)) != BINV_OK) goto out;
-  if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
-  if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
-  for (int k = 0;; ++k) {
-    if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
-    if (k < 8) inf.rho_steps[k] = rho;
-    if (rho <= target) { inf.converged = 1; break; }
-    const bool diverging = !(rho < 0.5) || (k > 0 && !(rho < inf.rho_steps[k - 1]));
-    if (diverging) {
-      // fall back to the plain FP64 sweep
-      inf.fell_back = 1;
+  {
+    const bool look = !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD));
+    const bool from64 = opts && (opts->flags & BINV_F_REFINE_FROM_FP64);
+    if (from64) {
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
-      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD)))) != BINV_OK)
-        goto out;
+      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK) goto out;
+    } else {
+      if ((st = sweep_f32(ctx, n, A, lda, X, ldx, part, s, dinfo)) != BINV_OK) goto out;
+    }
+    if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
+    if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
+    if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+    if (!(rho < 0.5) && !from64) {
+      // the FP32 sweep is too inaccurate for Newton-Schulz to converge: start
+      // again from the FP64 sweep (and refine that)
+      inf.fell_back = 1;
+      inf.rho_steps[0] = rho;
+      hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK) goto out;
       if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
       if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
       if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
-      inf.converged = rho <= target;
-      break;
     }
-    if (k >= max_refine) break;
-    // X <- X + X (I - A X)
-    {
-      PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
-      hipError_t e = binv::launch_gemm_f64(binv::kModeAdd, X, ldx, Res, n, X, ldx, Xn, n, n, s, nullptr);
-      if (e == hipSuccess) e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
-      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+    int hk = inf.fell_back ? 1 : 0;  // next free slot of rho_steps
+    if (hk < 8) inf.rho_steps[hk++] = rho;
+    for (int k = 0; rho > target && k < max_refine && rho < 0.5; ++k) {
+      // X <- X + X (I - A X)
+      {
+        PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
+        hipError_t e = binv::launch_gemm_f64(binv::kModeAdd, X, ldx, Res, n, X, ldx, Xn, n, n, s, nullptr);
+        if (e == hipSuccess) e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
+        if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+      }
+      inf.refine_steps = k + 1;
+      const double prev_rho = rho;
+      if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+      if (hk < 8) inf.rho_steps[hk++] = rho;
+      if (!(rho < prev_rho)) break;  // stagnated at the rounding floor (or diverging)
     }
-    inf.refine_steps = k + 1;
+    inf.converged = rho <= target;
   }
   inf.rho = rho;
 out:

@@ -58,16 +58,6 @@ struct LeafJob {
   int* info;  // the matrix's info word
 };
 
-// One column-panel save of a batch.
-struct ColJob {
-  const double* W;
-  int64_t ldw;
-  int64_t n;
-  int64_t o;
-  int b;
-  double* Ct;
-  int64_t ldc;
-};
 
 // kernels.hip
 hipError_t launch_leaf_inverse(const double* A, int64_t lda, double* P, int64_t ldp, int b, int64_t row0,
@@ -83,7 +73,6 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
                         int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
 hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s);
-hipError_t launch_col_save_batched(const ColJob* jobs, int64_t count, hipStream_t s);
 hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s);
 hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s);
 

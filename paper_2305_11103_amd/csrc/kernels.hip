@@ -230,18 +230,6 @@ __global__ void __launch_bounds__(256) k_col_save(const double* __restrict__ W, 
   }
 }
 
-// Batched column-panel save: workgroup i copies panel i (small matrices).
-
-__global__ void __launch_bounds__(256) k_col_save_batched(const ColJob* __restrict__ jobs) {
-  const ColJob j = jobs[blockIdx.x];
-  const int64_t total = (int64_t)j.b * j.n;
-  for (int64_t e = threadIdx.x; e < total; e += 256) {
-    const int64_t i = e / j.b;
-    const int t = (int)(e - i * j.b);
-    j.Ct[(int64_t)t * j.ldc + i] = j.W[i * j.ldw + j.o + t];
-  }
-}
-
 // ---------------------------------------------------------------------------
 // 2-D copy (out-of-place calls start from a copy of A).
 // ---------------------------------------------------------------------------
@@ -526,12 +514,24 @@ __attribute__((amdgpu_waves_per_eu(C::NT >= 512 ? 4 : 2, C::NT >= 512 ? 4 : 2)))
 }
 
 // Batched form: workgroup i runs every tile of problem args[i] (one small
-// matrix of a batch).
+// matrix of a batch).  For the Schur update the workgroup first copies the old
+// column panel W[:, o:o+b] (from Win) row-major into g.A (ld g.lda = b), which
+// is then the m-major contraction operand.
 template <int MODE, class C, bool A_KMAJOR>
 __global__ void __launch_bounds__(C::NT) k_gemm_step_batched(const StepArgs* __restrict__ args) {
   __shared__ double As[2][C::BK * C::LA];
   __shared__ double Bs[2][C::BK * C::LB];
   const StepArgs g = args[blockIdx.x];
+  if (MODE == MODE_SCHUR) {
+    double* Cp = const_cast<double*>(g.A);
+    const int64_t total = g.M * (int64_t)g.b;
+    for (int64_t e = threadIdx.x; e < total; e += C::NT) {
+      const int64_t i = e / g.b;
+      const int t = (int)(e - i * g.b);
+      Cp[i * g.lda + t] = g.Win[i * g.ldwin + g.o + t];
+    }
+    __syncthreads();
+  }
   const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
   for (int64_t tm = 0; tm < TM; ++tm)
     for (int64_t tn = 0; tn < TN; ++tn) gemm_tile<MODE, C, A_KMAJOR, false>(g, tm, tn, As, Bs);
@@ -712,12 +712,6 @@ hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hip
   return hipGetLastError();
 }
 
-hipError_t launch_col_save_batched(const ColJob* jobs, int64_t count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_col_save_batched, dim3((unsigned)count), dim3(256), 0, s, jobs);
-  return hipGetLastError();
-}
-
 hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_gemm_step_batched<MODE_ROW, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count), dim3(256), 0,
@@ -727,7 +721,7 @@ hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStre
 
 hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, true>), dim3((unsigned)count), dim3(256),
+  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count), dim3(256),
                      0, s, args);
   return hipGetLastError();
 }
