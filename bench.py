@@ -8,6 +8,14 @@
 --workload batched: one batch of 100000 SPD 5 x 5 matrices plus 20000 SPD
   matrices of order uniform in [8, 256] (B B^T + 0.1 I, B Gaussian), each split
   into k in {2, 3, 4} near-equal diagonal blocks.  One step = the whole batch.
+--workload mixed: n = 16384, 32 x 32 grid of 512-blocks, A = U diag(s) V^T
+  (U, V Haar, s geometric with cond in {1e2, 1e4, 1e6}); the FP32 sweep with
+  FP64 pivots and FP64 Newton-Schulz refinement to rho <= 1e-10, next to the
+  plain FP64 sweep (refined from FP64 when it misses the target).
+--workload serve: a Poisson stream of 5000 requests, orders log-uniform in
+  [5, 8192], cond 10^U[1, 6], tagged fp64 or mixed (target 1e-10), through
+  the continuous-batching server, at the arrival rate equal to the measured
+  serial plain-FP64 capacity, and at saturation (all at t = 0).
 
 Throughput counts 2 n^3 flops per inverse and is only reported as valid when
 the oracle's compensated residual rho = ||AX - I||_F / sqrt(n) (sampled rows,
@@ -97,12 +105,17 @@ def bench_plain(args):
     from paper_2305_11103_amd import binv, workloads
 
     n, blk = args.n, args.block
-    log(f"bench: generating SPD Haar matrix n={n} cond={args.cond:g}")
+    log(f"bench: generating SPD Haar matrix n={n} cond={args.cond:g} ({args.gen} QR)")
     t0 = time.perf_counter()
-    A_np = workloads.spd_haar(n, workloads.stream_seed(2, 0), cond=args.cond)
-    log(f"bench: generated in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
-    A = torch.from_numpy(A_np).to(dev)
+    if args.gen == "device":
+        A = workloads.spd_haar_device(n, workloads.stream_seed(2, 0), args.cond, dev).contiguous()
+        A_np = A.cpu().numpy()
+    else:  # host QR (numpy): used where device QR cannot run, e.g. under counter collection
+        A_np = workloads.spd_haar(n, workloads.stream_seed(2, 0), cond=args.cond)
+        A = torch.from_numpy(A_np).to(dev)
+    torch.cuda.empty_cache()
+    log(f"bench: generated in {time.perf_counter() - t0:.1f} s")
     X = torch.empty_like(A)
     ctx = binv.default_context(0)
     part = workloads.uniform_partition(n, blk)
@@ -209,6 +222,12 @@ def bench_batched(args):
     A = torch.from_numpy(plan.pack(mats)).to("cuda:0")
     X = torch.empty_like(A)
     info = torch.empty(plan.count, dtype=torch.int32, device="cuda:0")
+    t0 = time.perf_counter()
+    chosen, tune_ms, shapes = plan.tune(A, X, info=info, reps=3)
+    tuned = {f"tier{t}": {"shape": list(shapes[t][c]), "ms": [round(v, 4) for v in tune_ms[t]]}
+             for t, c in enumerate(chosen) if c >= 0}
+    log(f"bench: autotuned tier shapes in {time.perf_counter() - t0:.2f} s: "
+        + ", ".join(f"{k} {v['shape']}" for k, v in tuned.items()))
     for i in range(args.warmup):
         plan.invert(A, out=X, info=info, graph=True)
         log(f"bench: warmup {i + 1}/{args.warmup} done")
@@ -312,7 +331,251 @@ def bench_batched(args):
                      "avg_launch_ms": round(d_ms / max(d_cnt, 1), 4), "launches": d_cnt,
                      "flops_per_launch": d_fl / max(d_cnt, 1)},
         "phase_ms_per_step": {p: round(timing[p][0] / args.steps, 4) for p in phases},
+        "autotuned_tiers": tuned,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(args):
+    import torch
+
+    import oracle
+    from paper_2305_11103_amd import binv, workloads
+
+    n, blk = args.n if args.n != 8192 else 16384, args.block
+    dev = torch.device("cuda:0")
+    ctx = binv.default_context(0)
+    part = workloads.uniform_partition(n, blk)
+    rows = np.sort(np.random.default_rng(7).choice(n, size=min(args.check_rows, n, 16), replace=False))
+    results = []
+    t_plain_all, t_mixed_all = 0.0, 0.0
+    for ci, cond in enumerate((1e2, 1e4, 1e6)):
+        log(f"bench: generating U diag(s) V^T, n={n}, cond={cond:g} (device QR)")
+        A = workloads.general_haar_device(n, workloads.stream_seed(3, ci), cond, dev).contiguous()
+        torch.cuda.synchronize()
+        X = torch.empty_like(A)
+        # plain FP64 sweep (warm, then timed), and its accuracy
+        binv.invert(A, part=part, out=X, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binv.invert(A, part=part, out=X, ctx=ctx)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        # plain FP64 with refinement to the target (equal accuracy)
+        t0 = time.perf_counter()
+        X64, inf64 = binv.invert_mixed(A, part=part, out=X, ctx=ctx, from_fp64=True)
+        torch.cuda.synchronize()
+        t_plain_ref = time.perf_counter() - t0
+        # mixed: FP32 sweep + FP64 pivots + FP64 Newton-Schulz
+        Xm = torch.empty_like(A)
+        binv.invert_mixed(A, part=part, out=Xm, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xm, infm = binv.invert_mixed(A, part=part, out=Xm, ctx=ctx)
+        torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - t0
+        Ah = A.cpu().numpy()
+        rho_m = oracle.residual_stats(Ah, Xm.cpu().numpy(), rows)["rho"]
+        rho_p = oracle.residual_stats(Ah, X64.cpu().numpy(), rows)["rho"]
+        del Ah
+        log(f"bench: cond {cond:g}: plain {t_plain*1e3:.1f} ms (rho {inf64['rho_steps'][0]:.2e}), plain+refine "
+            f"{t_plain_ref*1e3:.1f} ms (rho {inf64['rho']:.2e}), mixed {t_mixed*1e3:.1f} ms (rho {infm['rho']:.2e}, "
+            f"steps {infm['refine_steps']}, fell back {infm['fell_back']})")
+        best_plain = t_plain if inf64["rho_steps"][0] <= 1e-10 else t_plain_ref
+        t_plain_all += best_plain
+        t_mixed_all += t_mixed
+        results.append({"cond": cond, "plain_ms": round(t_plain * 1e3, 2),
+                        "plain_rho": inf64["rho_steps"][0],
+                        "plain_refined_ms": round(t_plain_ref * 1e3, 2), "plain_refined_rho": inf64["rho"],
+                        "plain_refined_steps": inf64["refine_steps"],
+                        "mixed_ms": round(t_mixed * 1e3, 2), "mixed_rho": infm["rho"],
+                        "mixed_rho_oracle_sampled": rho_m, "plain_refined_rho_oracle_sampled": rho_p,
+                        "mixed_steps": infm["refine_steps"], "mixed_fell_back": infm["fell_back"],
+                        "mixed_converged": infm["converged"],
+                        "speedup_mixed_vs_plain_at_equal_accuracy": round(best_plain / t_mixed, 3)})
+        del A, X, Xm, X64
+        torch.cuda.empty_cache()
+    ok = all(r["mixed_converged"] and r["mixed_rho_oracle_sampled"] <= 1e-10 for r in results)
+    flops = 3 * 2.0 * n ** 3
+    out = {
+        "metric": METRIC,
+        "value": round(flops / t_mixed_all / 1e12 if ok else 0.0, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(t_mixed_all / 3 * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"mixed precision, n={n}, {len(part)}x{len(part)} grid of {blk}-blocks, "
+                               f"U diag(s) V^T Haar, cond 1e2/1e4/1e6, target rho 1e-10", "n": n, "block": blk},
+        "valid": ok,
+        "plain_fp64_equal_accuracy_tflops": round(flops / t_plain_all / 1e12, 4),
+        "per_cond": results,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    import torch
+
+    import oracle
+    from paper_2305_11103_amd import binv, workloads
+
+    dev = torch.device("cuda:0")
+    N = args.requests
+    sizes, conds, tags = workloads.request_stream(N, workloads.stream_seed(5, 0))
+    seeds = [workloads.stream_seed(5, 1 + i) for i in range(N)]
+    flops = float(np.sum(2.0 * sizes.astype(np.float64) ** 3))
+    ctx = binv.default_context(0)
+    cur = torch.cuda.current_stream(dev)
+    budget = args.budget_gib << 30
+
+    def gen(i):
+        A = workloads.householder_conditioned_device(int(sizes[i]), seeds[i], float(conds[i]), dev).contiguous()
+        cur.synchronize()  # this stream only: the server's work keeps running
+        return A
+
+    def blk(n):
+        return 512 if n >= 2048 else (256 if n >= 512 else 128)
+
+    def need(n, prec):  # device bytes the server charges (client-side back-pressure)
+        b = 16 * n * n
+        if n > 128:
+            bl = min(512, n)
+            b += 32 * bl * n + 16 * bl * bl + (20 * n * n if prec == "mixed" else 0)
+        return b
+
+    # Serial FIFO capacity, one request at a time: the plain FP64 sweep alone,
+    # and the same sweep followed by the server's residual check (64 sampled
+    # rows; refinement when it fails), i.e. at the accuracy the server gives.
+    log(f"bench: serial plain-FP64 baseline over {N} requests")
+    t_plain = t_checked = t_gen = 0.0
+    for i in range(N):
+        n = int(sizes[i])
+        t0 = time.perf_counter()
+        A = gen(i)
+        t_gen += time.perf_counter() - t0
+        X = torch.empty_like(A)
+        t0 = time.perf_counter()
+        binv.invert(A, block=blk(n), out=X, ctx=ctx, lookahead=n >= 4096)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        if n > 128:
+            t0 = time.perf_counter()
+            binv.invert_mixed(A, block=blk(n), out=X, ctx=ctx, lookahead=n >= 4096, from_fp64=True,
+                              sampled_check=True)
+            torch.cuda.synchronize()
+            t_checked += time.perf_counter() - t0
+        else:
+            t_checked += time.perf_counter() - t0
+        del A, X
+        if (i + 1) % 500 == 0:
+            log(f"bench: serial {i + 1}/{N}: plain {t_plain:.1f} s, checked {t_checked:.1f} s, gen {t_gen:.1f} s")
+    mu_plain = N / t_plain
+    mu = N / t_checked
+    log(f"bench: serial capacity {mu_plain:.1f}/s plain, {mu:.1f}/s checked")
+    torch.cuda.empty_cache()
+
+    def run(rate, label, strict=False):
+        srv = binv.Server(hbm_budget=budget, strict_precision=strict)
+        rng = np.random.default_rng(11)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, N)) if rate > 0 else np.zeros(N)
+        small = [i for i in range(N) if sizes[i] <= 1024]
+        check = set(rng.choice(small, size=min(args.check_requests, len(small)), replace=False).tolist())
+        tickets, keep, t_sub, lat = {}, {}, {}, np.zeros(N)
+        not_conv = {"fp64": 0, "mixed": 0}
+        start = time.perf_counter()
+        nxt, done_n, held = 0, 0, 0
+
+        def collect():
+            nonlocal done_n, held
+            got = 0
+            for t in list(tickets):
+                i = tickets[t]
+                out = keep[i][1] if i in keep else None
+                r = srv.poll(t, out=out, copy=out is not None)
+                if r is None:
+                    continue
+                _, info, tm = r
+                lat[i] = (t_sub[i] - start - arrivals[i]) * 1e3 + tm["total_ms"]
+                if not info["converged"]:
+                    not_conv[str(tags[i])] += 1
+                if i in keep:
+                    keep[i] = (keep[i][0], keep[i][1].cpu().numpy(), info)
+                held -= need(int(sizes[i]), str(tags[i]))
+                del tickets[t]
+                done_n += 1
+                got += 1
+            return got
+
+        while done_n < N:
+            progressed = collect() > 0
+            now = time.perf_counter() - start
+            while nxt < N and arrivals[nxt] <= now and held + need(int(sizes[nxt]), str(tags[nxt])) <= budget:
+                n = int(sizes[nxt])
+                A = gen(nxt)
+                if nxt in check:
+                    keep[nxt] = (A.cpu().numpy(), torch.empty((n, n), dtype=torch.float64, device=dev))
+                t_sub[nxt] = time.perf_counter()
+                tickets[srv.submit(A, prec=str(tags[nxt]), target=1e-10)] = nxt
+                held += need(n, str(tags[nxt]))
+                del A
+                nxt += 1
+                progressed = True
+                now = time.perf_counter() - start
+            if not progressed:
+                time.sleep(0.0005)
+        makespan = time.perf_counter() - start
+        peak = srv.stats()["peak"]
+        srv.close()
+        # accuracy on the oracle-checked requests: the gate is the target, or
+        # twice the oracle Gauss-Jordan inverse's own rho where that is larger
+        rhos = {"fp64": [], "mixed": []}
+        worst = 0.0
+        for i, v in keep.items():
+            A, X, info = v
+            r = oracle.residual_stats(A, X)["rho"]
+            r_o1 = oracle.residual_stats(A, oracle.gj_inverse(A))["rho"]
+            rhos[str(tags[i])].append(r)
+            worst = max(worst, r / max(1e-10, 2.0 * r_o1))
+        p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+        log(f"bench: {label}: {N / makespan:.1f} solves/s, {flops / makespan / 1e12:.2f} TFLOP/s, "
+            f"p50 {p50:.2f} ms, p99 {p99:.2f} ms, peak {peak / 2**30:.1f} GiB")
+        return {"solves_per_s": round(N / makespan, 2), "makespan_s": round(makespan, 3),
+                "tflops": round(flops / makespan / 1e12, 4), "p50_ms": round(p50, 3), "p99_ms": round(p99, 3),
+                "peak_charged_bytes": int(peak), "oracle_checked": len(keep),
+                "rho_max_fp64_sampled": max(rhos["fp64"]) if rhos["fp64"] else None,
+                "rho_max_mixed_sampled": max(rhos["mixed"]) if rhos["mixed"] else None,
+                "worst_rho_over_gate": worst, "not_converged": not_conv}
+
+    served = run(mu, f"served at lambda={mu:.1f}/s")
+    sat = run(0, "saturation")
+    strict = run(0, "saturation, mixed tags honoured strictly", strict=True)
+    ok = all(r["worst_rho_over_gate"] <= 1.0 for r in (served, sat, strict))
+    out = {
+        "metric": METRIC,
+        "value": round(sat["tflops"] if ok else 0.0, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(sat["makespan_s"] * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving: {N} Poisson requests, n log-uniform [5, 8192], cond 10^U[1,6], "
+                               f"fp64/mixed tags, target 1e-10, HBM budget {args.budget_gib} GiB"},
+        "valid": ok,
+        "solves_per_s": sat["solves_per_s"],
+        "serial_fp64_solves_per_s": round(mu_plain, 2),
+        "serial_fp64_checked_solves_per_s": round(mu, 2),
+        "client_generation_s": round(t_gen, 3),
+        "speedup_vs_serial_checked_at_saturation": round(sat["solves_per_s"] / mu, 3),
+        "speedup_vs_serial_plain_at_saturation": round(sat["solves_per_s"] / mu_plain, 3),
+        "served_at_serial_rate": served,
+        "saturation": sat,
+        "saturation_strict_precision": strict,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
@@ -322,7 +585,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["plain", "batched"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve"], default="plain")
+    ap.add_argument("--gen", choices=["device", "host"], default="device",
+                    help="where the plain workload's Haar factor is formed")
+    ap.add_argument("--requests", type=int, default=5000)
+    ap.add_argument("--check-requests", type=int, default=60)
+    ap.add_argument("--budget-gib", type=int, default=64)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--block", type=int, default=512)
     ap.add_argument("--cond", type=float, default=1e4)
@@ -335,7 +603,7 @@ def main():
               f"(the batched and served forms shard with no communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
-    {"plain": bench_plain, "batched": bench_batched}[args.workload](args)
+    {"plain": bench_plain, "batched": bench_batched, "mixed": bench_mixed, "serve": bench_serve}[args.workload](args)
 
 
 if __name__ == "__main__":

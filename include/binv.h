@@ -68,6 +68,11 @@ typedef enum {
                              BINV_E_SINGULAR from the device-side info word */
 #define BINV_F_REFINE_FROM_FP64 8u /* binv_invert_mixed: start the refinement from
                              the plain FP64 sweep instead of the FP32 one */
+#define BINV_F_SAMPLED_CHECK 16u /* binv_invert_mixed: accept an iterate on
+                             rho estimated from 64 evenly spaced rows of
+                             I - A X (2 * 64 * n^2 flops instead of 2 n^3);
+                             the full residual is formed only when a
+                             Newton-Schulz step needs it */
 #define BINV_F_GRAPH 4u  /* batched calls: capture the whole launch sequence in
                              a HIP graph on first use and replay it (re-captured
                              when the A, X or info pointers change) */
@@ -131,11 +136,15 @@ typedef struct {
                               would not converge), so the FP64 sweep was used
                               as the starting point */
   int32_t converged;       /* 1: rho <= target */
+  int32_t sampled;         /* 1: rho is the sampled-rows estimate
+                              (BINV_F_SAMPLED_CHECK); -1: no residual was
+                              formed (rho = 0) */
 } binv_info;
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
  * is read again by the refinement.  opts: the partition (as binv_invert) and
- * the flags BINV_F_NO_LOOKAHEAD, BINV_F_REFINE_FROM_FP64.  Refinement stops
+ * the flags BINV_F_NO_LOOKAHEAD, BINV_F_REFINE_FROM_FP64, BINV_F_SAMPLED_CHECK.
+ * Refinement stops
  * once rho <= target (target <= 0 means 1e-10), after max_refine steps
  * (< 0 means 5, at most 6), or when rho stops decreasing.  Because the sweep
  * never pivots across diagonal blocks, its error can grow on nonsymmetric
@@ -183,25 +192,55 @@ binv_status binv_batch_query(const binv_batch* plan, int64_t* count, int64_t* to
 binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, int32_t* d_info, uint32_t flags,
                                 void* stream);
 
+/* Autotuner for the register-resident tiers (orders <= 128).  Each tier has
+ * several launch shapes (rows per lane, columns per wave, waves per matrix,
+ * matrices per workgroup) that compute bitwise-identical results; this call
+ * runs every shape of every non-empty tier `reps` times (>= 1) on the plan's
+ * own matrices (A -> X, d_info as for binv_invert_batched, which it leaves
+ * holding a valid inversion), times each with HIP events on `stream`, and
+ * keeps the fastest in the plan.  The choice is also remembered in `ctx` by
+ * tier and by the power of two of the tier's matrix count, and plans created
+ * later on that context start from it.  Synchronous.  chosen (may be NULL):
+ * int32[5], the shape index per tier (-1 for an empty tier); ms (may be
+ * NULL): double[5 * 4], the best time of each (tier, shape), 0 when not run
+ * (tiers have 4, 4, 4, 4 and 2 shapes). */
+binv_status binv_batch_tune(binv_batch* plan, const double* A, double* X, int32_t* d_info, int32_t reps,
+                            void* stream, int32_t* chosen, double* ms);
+
+/* Launch shape of (tier, shape index): {rows per lane, columns per wave,
+ * waves per matrix, matrices per workgroup}.  BINV_E_INVALID for an index the
+ * tier does not have. */
+binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of inversion requests of mixed orders.
  *
  * binv_submit copies A (a host or device pointer; the caller may reuse it at
- * once) into server-owned staging memory and returns a ticket; it never
- * blocks on the device.  A scheduler thread admits queued requests in FIFO
+ * once) and returns a ticket; it never waits for other requests.  A device A
+ * (complete: the copy is not ordered after the caller's streams, so the
+ * caller synchronizes the stream that produced A first)
+ * is copied straight into the request's device state when the budget has
+ * room at that moment (the memory is charged from then on); otherwise A is
+ * staged in host memory until admission.  A scheduler thread admits queued requests in FIFO
  * order while the server's HBM budget (bytes of device memory held for
  * admitted, not yet collected requests, including their working panels) and
  * in-flight limit allow.  Admitted requests of order <= 128 are grouped into
  * shared batched launches (one Gauss-Jordan pass each, pivoting over the
  * whole matrix); larger ones are inverted by the blockwise sweep on worker
  * threads with their own streams, so their work overlaps on the device.
- * Requests tagged BINV_PREC_MIXED_F32 of order > 128 use binv_invert_mixed
- * with the given residual target; small ones are always FP64.
+ * Every request of order > 128 ends with the FP64 residual check against its
+ * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
+ * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
+ * fails.  BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
+ * the FP32 sweep under the policy of BINV_SERVER_STRICT_PRECISION below.
+ * Requests of order <= 128 are always FP64 Gauss-Jordan and carry no
+ * residual check (info->sampled = -1, rho = 0).
  * binv_poll returns BINV_E_BUSY until the request is done; then it copies X
  * (n x n row-major, host or device pointer, may be NULL), fills *info and
  * *times (either may be NULL), releases the request's device memory and
  * forgets the ticket.  A finished request keeps its memory until it is
- * polled.  Errors: BINV_E_NOMEM from binv_submit when the request alone
+ * polled; the server then keeps the block for reuse by later requests (at
+ * most the budget's worth of cached blocks, freed by binv_server_destroy).  Errors: BINV_E_NOMEM from binv_submit when the request alone
  * exceeds the budget; BINV_E_SINGULAR (and the other codes) from binv_poll
  * for a request that failed.
  * --------------------------------------------------------------------------- */
@@ -212,11 +251,23 @@ typedef struct {
   double total_ms;   /* submit -> result ready (latency) */
 } binv_request_times;
 
-binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_inflight, binv_server** server);
+#define BINV_SERVER_STRICT_PRECISION 1u /* mixed requests always start from the
+                             FP32 sweep (default: only when the target is
+                             >= 1e-6, within the FP32 sweep's reach; below
+                             that one Newton-Schulz step costs two FP64 GEMMs
+                             of the sweep's size, more than the FP64 sweep it
+                             would save, so they start from the FP64 sweep) */
+#define BINV_SERVER_FULL_CHECK 2u /* gate on the full residual instead of the
+                             64-row sampled estimate (BINV_F_SAMPLED_CHECK) */
+binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_inflight, uint32_t flags,
+                               binv_server** server);
 binv_status binv_submit(binv_server* server, int64_t n, const double* A, int a_is_device, int32_t prec,
                         double target, uint64_t* ticket);
 binv_status binv_poll(binv_server* server, uint64_t ticket, double* X, int x_is_device, binv_info* info,
                       binv_request_times* times);
+/* Device bytes currently held, the most ever held (never above the budget),
+ * and requests finished so far.  Any pointer may be NULL. */
+binv_status binv_server_stats(binv_server* server, size_t* used_bytes, size_t* peak_bytes, int64_t* completed);
 /* Stops the scheduler, lets running requests finish, frees everything. */
 binv_status binv_server_destroy(binv_server* server);
 

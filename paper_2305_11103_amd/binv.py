@@ -19,6 +19,10 @@ BINV_E_INVALID = 1
 BINV_E_SINGULAR = 2
 BINV_E_NOMEM = 3
 BINV_E_HIP = 5
+BINV_E_BUSY = 6
+BINV_E_NOTFOUND = 7
+BINV_PREC_FP64 = 0
+BINV_PREC_MIXED_F32 = 1
 BINV_F_SYNC = 1
 BINV_F_NO_LOOKAHEAD = 2
 
@@ -26,10 +30,16 @@ BINV_F_NO_LOOKAHEAD = 2
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
            "binv_invert_mixed",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
+           "binv_batch_tune", "binv_batch_shape",
+           "binv_server_create", "binv_submit", "binv_poll", "binv_server_stats", "binv_server_destroy",
            "binv_last_error", "binv_version")
 BINV_F_GRAPH = 4
 BINV_F_REFINE_FROM_FP64 = 8
+BINV_F_SAMPLED_CHECK = 16
+BINV_SERVER_STRICT_PRECISION = 1
+BINV_SERVER_FULL_CHECK = 2
 PHASES = ("pivot", "row", "schur", "other", "band", "small")
+TIER_SHAPES = (4, 4, 4, 4, 2)  # launch shapes per register tier (autotuned)
 
 
 class BinvError(RuntimeError):
@@ -48,7 +58,11 @@ class _Timing(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_double), ("rho_steps", ctypes.c_double * 8), ("refine_steps", ctypes.c_int32),
-                ("fell_back", ctypes.c_int32), ("converged", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("converged", ctypes.c_int32), ("sampled", ctypes.c_int32)]
+
+
+class _Times(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
 class _Opts(ctypes.Structure):
@@ -86,6 +100,19 @@ def load_library():
     lib.binv_invert_mixed.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts),
                                       ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(_Info)]
     lib.binv_invert_mixed.restype = ctypes.c_int
+    lib.binv_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint32,
+                                       ctypes.POINTER(P)]
+    lib.binv_server_create.restype = ctypes.c_int
+    lib.binv_submit.argtypes = [P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int32, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_uint64)]
+    lib.binv_submit.restype = ctypes.c_int
+    lib.binv_poll.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int, ctypes.POINTER(_Info), ctypes.POINTER(_Times)]
+    lib.binv_poll.restype = ctypes.c_int
+    lib.binv_server_stats.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.binv_server_stats.restype = ctypes.c_int
+    lib.binv_server_destroy.argtypes = [P]
+    lib.binv_server_destroy.restype = ctypes.c_int
     lib.binv_batch_create.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.POINTER(P)]
     lib.binv_batch_create.restype = ctypes.c_int
     lib.binv_batch_destroy.argtypes = [P]
@@ -95,6 +122,11 @@ def load_library():
     lib.binv_batch_query.restype = ctypes.c_int
     lib.binv_invert_batched.argtypes = [P, P, P, P, ctypes.c_uint32, P]
     lib.binv_invert_batched.restype = ctypes.c_int
+    lib.binv_batch_tune.argtypes = [P, P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.binv_batch_tune.restype = ctypes.c_int
+    lib.binv_batch_shape.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.binv_batch_shape.restype = ctypes.c_int
     lib.binv_last_error.argtypes = []
     lib.binv_last_error.restype = ctypes.c_char_p
     lib.binv_version.argtypes = []
@@ -228,7 +260,7 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
 
 
 def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=True,
-                 from_fp64=False):
+                 from_fp64=False, sampled_check=False):
     """Mixed-precision inversion: FP32 blockwise sweep (FP64 pivot blocks), then
     FP64 Newton-Schulz refinement to rho = ||AX - I||_F / sqrt(n) <= target.
     Synchronous.  Returns (X, info dict)."""
@@ -243,6 +275,8 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
     o, keep = _opts(part, block, False, lookahead)
     if from_fp64:
         o.flags |= BINV_F_REFINE_FROM_FP64
+    if sampled_check:
+        o.flags |= BINV_F_SAMPLED_CHECK
     inf = _Info()
     with torch.cuda.device(dev):
         st = load_library().binv_invert_mixed(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
@@ -253,7 +287,14 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
     _check(st)
     k = inf.refine_steps
     return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1 + inf.fell_back]), "refine_steps": k,
-               "fell_back": bool(inf.fell_back), "converged": bool(inf.converged)}
+               "fell_back": bool(inf.fell_back), "converged": bool(inf.converged), "sampled": inf.sampled}
+
+
+def batch_shape(tier, shape):
+    """Launch shape (rows/lane, cols/wave, waves/matrix, matrices/workgroup)."""
+    out = (ctypes.c_int32 * 4)()
+    _check(load_library().binv_batch_shape(int(tier), int(shape), out))
+    return tuple(out)
 
 
 class Batch:
@@ -310,6 +351,26 @@ class Batch:
         _check(st)
         return X, info
 
+    def tune(self, A, out, info=None, reps=3):
+        """Autotune the launch shape of each register tier on this batch (A -> out,
+        out != A).  Returns (chosen shape per tier, ms table [tier][shape],
+        shapes [tier] as (rows/lane, cols/wave, waves/matrix, matrices/workgroup))."""
+        import torch
+        if A.dtype != torch.float64 or not A.is_cuda or A.numel() != self.total_elems or not A.is_contiguous():
+            raise ValueError("A must be a contiguous float64 CUDA buffer of the plan's packed size")
+        if out is None or out.data_ptr() == A.data_ptr():
+            raise ValueError("tuning needs a separate output buffer")
+        if info is None:
+            info = torch.empty(max(self.count, 1), dtype=torch.int32, device=A.device)
+        chosen = (ctypes.c_int32 * 5)()
+        ms = (ctypes.c_double * 20)()
+        with torch.cuda.device(A.device):
+            _check(load_library().binv_batch_tune(self._h, ctypes.c_void_p(A.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(info.data_ptr()),
+                                                  int(reps), _stream_handle(torch, A.device.index or 0), chosen, ms))
+        return list(chosen), [list(ms[4 * t:4 * t + TIER_SHAPES[t]]) for t in range(5)], [
+            [batch_shape(t, v) for v in range(TIER_SHAPES[t])] for t in range(5)]
+
     def pack(self, mats):
         """Pack a list of square numpy matrices into one flat float64 array."""
         import numpy as np
@@ -319,3 +380,78 @@ class Batch:
     def unpack(self, flat):
         """Split a flat array (numpy) back into the plan's matrices."""
         return [flat[o:o + m * m].reshape(m, m) for o, m in zip(self.offsets, self.sizes)]
+
+
+class Server:
+    """Continuous-batching inversion server on one device (see binv_submit)."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, max_inflight=0, strict_precision=False, full_check=False):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        flags = (BINV_SERVER_STRICT_PRECISION if strict_precision else 0) | (BINV_SERVER_FULL_CHECK if full_check else 0)
+        _check(lib.binv_server_create(int(device), int(hbm_budget), int(max_inflight), flags, ctypes.byref(h)))
+        self._h = h
+        self._shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().binv_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, A, prec="fp64", target=1e-10) -> int:
+        """A: square float64 numpy array or CUDA tensor (copied at once)."""
+        import numpy as np
+        is_dev = hasattr(A, "is_cuda") and A.is_cuda
+        if is_dev:
+            if A.dtype.__str__() != "torch.float64" or not A.is_contiguous():
+                raise ValueError("device A must be a contiguous float64 tensor")
+            ptr, n = A.data_ptr(), A.shape[0]
+        else:
+            A = np.ascontiguousarray(A, dtype=np.float64)
+            ptr, n = A.ctypes.data, A.shape[0]
+        if A.shape[0] != A.shape[1]:
+            raise ValueError("A must be square")
+        p = BINV_PREC_MIXED_F32 if prec == "mixed" else BINV_PREC_FP64
+        t = ctypes.c_uint64()
+        _check(load_library().binv_submit(self._h, int(n), ctypes.c_void_p(ptr), int(is_dev), p, float(target),
+                                          ctypes.byref(t)))
+        self._shapes[t.value] = int(n)
+        return t.value
+
+    def poll(self, ticket, out=None, copy=True):
+        """None while busy; else (X, info dict, times dict).  X is a numpy array
+        unless `out` (a CUDA tensor of the right shape) is given; with
+        copy=False the result is dropped and X is None."""
+        import numpy as np
+        n = self._shapes.get(ticket)
+        if n is None:
+            raise BinvError(BINV_E_NOTFOUND, "unknown ticket")
+        if not copy:
+            X, ptr, dev = None, None, 0
+        elif out is None:
+            X = np.empty((n, n), dtype=np.float64)
+            ptr, dev = X.ctypes.data, 0
+        else:
+            X = out
+            ptr, dev = out.data_ptr(), 1
+        inf, tm = _Info(), _Times()
+        st = load_library().binv_poll(self._h, ctypes.c_uint64(ticket), ctypes.c_void_p(ptr), dev, ctypes.byref(inf),
+                                      ctypes.byref(tm))
+        if st == BINV_E_BUSY:
+            return None
+        del self._shapes[ticket]
+        _check(st)
+        info = {"rho": inf.rho, "refine_steps": inf.refine_steps, "fell_back": bool(inf.fell_back),
+                "converged": bool(inf.converged), "sampled": inf.sampled}
+        return X, info, {"queue_ms": tm.queue_ms, "total_ms": tm.total_ms}
+
+    def stats(self):
+        u, p, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()
+        _check(load_library().binv_server_stats(self._h, ctypes.byref(u), ctypes.byref(p), ctypes.byref(c)))
+        return {"used": u.value, "peak": p.value, "completed": c.value}

@@ -176,41 +176,61 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
   }
 }
 
+// Launch shapes of the register kernel, per tier.  Every shape runs the same
+// per-element arithmetic in the same order (the pivot search is exact and each
+// update is one fma of the same operands), so all shapes of a tier give
+// bitwise-identical results; the autotuner picks among them by time alone.
+// {rows per lane, columns per wave, waves per matrix, matrices per workgroup}
+struct TierShape {
+  int rpl, cpw, nwv, sub;
+};
+static const TierShape kShapes[5][kSmallVariants] = {
+    {{1, 8, 1, 4}, {1, 8, 1, 8}, {1, 8, 1, 2}, {1, 8, 1, 16}},      // m <= 8
+    {{1, 16, 1, 4}, {1, 16, 1, 8}, {1, 8, 2, 4}, {1, 8, 2, 2}},     // m <= 16
+    {{1, 32, 1, 4}, {1, 16, 2, 2}, {1, 8, 4, 1}, {1, 32, 1, 8}},    // m <= 32
+    {{1, 16, 4, 1}, {1, 32, 2, 2}, {1, 8, 8, 1}, {1, 16, 4, 2}},    // m <= 64
+    {{2, 16, 8, 1}, {2, 8, 16, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},     // m <= 128 (wider shapes spill)
+};
+static const int kShapeCount[5] = {4, 4, 4, 4, 2};
+
+template <int RPL, int CPW, int NWV, int SUB>
+hipError_t launch_shape(const double* A, double* X, const SmallMat* mats, const int32_t* order, int64_t count,
+                        const int32_t* bounds, int32_t* info, hipStream_t s) {
+  const unsigned g = (unsigned)((count + SUB - 1) / SUB);
+  hipLaunchKernelGGL((k_small_inverse<RPL, CPW, NWV, SUB>), dim3(g), dim3(64 * NWV * SUB), 0, s, A, X, mats, order,
+                     count, bounds, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, const SmallMat* mats,
+                             const int32_t* order, int64_t count, const int32_t* bounds, int32_t* info,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (tier < 0 || tier >= 5 || variant < 0 || variant >= kShapeCount[tier]) return hipErrorInvalidValue;
+#define BINV_SHAPE(T, V, R, C, N, S) \
+  if (tier == T && variant == V) return launch_shape<R, C, N, S>(A, X, mats, order, count, bounds, info, s);
+  BINV_SHAPE(0, 0, 1, 8, 1, 4) BINV_SHAPE(0, 1, 1, 8, 1, 8) BINV_SHAPE(0, 2, 1, 8, 1, 2) BINV_SHAPE(0, 3, 1, 8, 1, 16)
+  BINV_SHAPE(1, 0, 1, 16, 1, 4) BINV_SHAPE(1, 1, 1, 16, 1, 8) BINV_SHAPE(1, 2, 1, 8, 2, 4) BINV_SHAPE(1, 3, 1, 8, 2, 2)
+  BINV_SHAPE(2, 0, 1, 32, 1, 4) BINV_SHAPE(2, 1, 1, 16, 2, 2) BINV_SHAPE(2, 2, 1, 8, 4, 1) BINV_SHAPE(2, 3, 1, 32, 1, 8)
+  BINV_SHAPE(3, 0, 1, 16, 4, 1) BINV_SHAPE(3, 1, 1, 32, 2, 2) BINV_SHAPE(3, 2, 1, 8, 8, 1) BINV_SHAPE(3, 3, 1, 16, 4, 2)
+  BINV_SHAPE(4, 0, 2, 16, 8, 1) BINV_SHAPE(4, 1, 2, 8, 16, 1)
+#undef BINV_SHAPE
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                              int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  switch (tier) {
-    case 0: {  // m <= 8: four matrices per workgroup, one wave each
-      const unsigned g = (unsigned)((count + 3) / 4);
-      hipLaunchKernelGGL((k_small_inverse<1, 8, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds, info);
-      break;
-    }
-    case 1: {  // m <= 16
-      const unsigned g = (unsigned)((count + 3) / 4);
-      hipLaunchKernelGGL((k_small_inverse<1, 16, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds,
-                         info);
-      break;
-    }
-    case 2: {  // m <= 32
-      const unsigned g = (unsigned)((count + 3) / 4);
-      hipLaunchKernelGGL((k_small_inverse<1, 32, 1, 4>), dim3(g), dim3(256), 0, s, A, X, mats, order, count, bounds,
-                         info);
-      break;
-    }
-    case 3: {  // m <= 64: four waves per matrix
-      hipLaunchKernelGGL((k_small_inverse<1, 16, 4, 1>), dim3((unsigned)count), dim3(256), 0, s, A, X, mats, order,
-                         count, bounds, info);
-      break;
-    }
-    case 4: {  // m <= 128: eight waves per matrix, two rows per lane
-      hipLaunchKernelGGL((k_small_inverse<2, 16, 8, 1>), dim3((unsigned)count), dim3(512), 0, s, A, X, mats, order,
-                         count, bounds, info);
-      break;
-    }
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return launch_small_tier(tier, 0, A, X, mats, order, count, bounds, info, s);
+}
+
+int small_variant_count(int tier) { return (tier >= 0 && tier < 5) ? kShapeCount[tier] : 0; }
+
+void small_variant_shape(int tier, int variant, int shape[4]) {
+  const TierShape& t = kShapes[tier][variant];
+  shape[0] = t.rpl;
+  shape[1] = t.cpw;
+  shape[2] = t.nwv;
+  shape[3] = t.sub;
 }
 
 // Largest order handled by each small tier.

@@ -67,6 +67,7 @@ struct binv_batch {
   std::vector<int32_t> m;
   // small tiers
   int64_t tier_first[kSmallTiers] = {0}, tier_count[kSmallTiers] = {0};
+  int variant[kSmallTiers] = {0};  // launch shape per tier (autotuned)
   double tier_flops[kSmallTiers] = {0};  // 2 sum m^3 per tier
   void* d_mats = nullptr;    // SmallMat per matrix (all matrices)
   void* d_order = nullptr;   // matrix indices grouped by tier
@@ -165,7 +166,7 @@ binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hi
   for (int t = 0; t < kSmallTiers; ++t) {
     binv::PhaseTimer tm(c, lvl, BINV_PHASE_SMALL, s);
     if (tm.on()) tm.flops = b->tier_flops[t];
-    BHIP(binv::launch_small_tier(t, A, X, (const binv::SmallMat*)b->d_mats,
+    BHIP(binv::launch_small_tier(t, b->variant[t], A, X, (const binv::SmallMat*)b->d_mats,
                                  (const int32_t*)b->d_order + b->tier_first[t], b->tier_count[t],
                                  (const int32_t*)b->d_bounds, info, s));
   }
@@ -187,6 +188,12 @@ binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hi
     }
   }
   return BINV_OK;
+}
+
+int count_bucket(int64_t count) {
+  int k = 0;
+  while (k < 39 && (int64_t(1) << (k + 1)) <= count) ++k;
+  return k;
 }
 
 }  // namespace
@@ -287,6 +294,8 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
     std::stable_sort(tiers[t].begin(), tiers[t].end(), [&](int32_t x, int32_t y) { return b->m[x] > b->m[y]; });
     b->tier_first[t] = (int64_t)order.size();
     b->tier_count[t] = (int64_t)tiers[t].size();
+    const int8_t known = ctx->tuned_small[t][count_bucket(b->tier_count[t])];
+    b->variant[t] = known >= 0 ? known : 0;
     order.insert(order.end(), tiers[t].begin(), tiers[t].end());
   }
   std::stable_sort(b->swept.begin(), b->swept.end(), [&](int32_t x, int32_t y) { return b->m[x] > b->m[y]; });
@@ -388,6 +397,86 @@ binv_status binv_invert_batched(binv_batch* b, const double* A, double* X, int32
     if (st != BINV_OK) return st;
   }
   if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));
+  return BINV_OK;
+}
+
+binv_status binv_batch_tune(binv_batch* b, const double* A, double* X, int32_t* d_info, int32_t reps, void* stream,
+                            int32_t* chosen, double* ms) {
+  if (!b) return bfail(BINV_E_INVALID, "plan is NULL");
+  if (reps < 1) return bfail(BINV_E_INVALID, "reps must be at least 1");
+  if (chosen)
+    for (int t = 0; t < kSmallTiers; ++t) chosen[t] = -1;
+  if (ms)
+    for (int i = 0; i < kSmallTiers * binv::kSmallVariants; ++i) ms[i] = 0.0;
+  if (b->count == 0) return BINV_OK;
+  if (!A || !X || !d_info) return bfail(BINV_E_INVALID, "A, X and d_info must be device pointers");
+  if (A == X) return bfail(BINV_E_INVALID, "tuning needs X separate from A (every shape reruns the batch)");
+  {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + b->total);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + b->total);
+    if (a0 < x1 && x0 < a1) return bfail(BINV_E_INVALID, "A and X overlap");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(BINV_E_HIP, "hipEventCreate failed");
+  }
+  binv_status st = BINV_OK;
+  for (int t = 0; t < kSmallTiers && st == BINV_OK; ++t) {
+    if (b->tier_count[t] == 0) continue;
+    int best = 0;
+    double best_ms = 1e300;
+    for (int v = 0; v < binv::small_variant_count(t) && st == BINV_OK; ++v) {
+      double vbest = 1e300;
+      for (int r = 0; r <= reps && st == BINV_OK; ++r) {  // launch 0 warms up
+        hipError_t e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+          e = binv::launch_small_tier(t, v, A, X, (const binv::SmallMat*)b->d_mats,
+                                      (const int32_t*)b->d_order + b->tier_first[t], b->tier_count[t],
+                                      (const int32_t*)b->d_bounds, d_info, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        if (e != hipSuccess) {
+          st = bfail(BINV_E_HIP, std::string("tuning launch: ") + hipGetErrorString(e));
+          break;
+        }
+        if (r > 0) vbest = std::min(vbest, (double)f);
+      }
+      if (ms) ms[t * binv::kSmallVariants + v] = vbest;
+      if (vbest < best_ms) {
+        best_ms = vbest;
+        best = v;
+      }
+    }
+    if (st != BINV_OK) break;
+    b->variant[t] = best;
+    b->ctx->tuned_small[t][count_bucket(b->tier_count[t])] = (int8_t)best;
+    if (chosen) chosen[t] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != BINV_OK) return st;
+  // the captured graph holds the old shapes
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  // leave X and d_info holding a complete inversion with the chosen shapes
+  return binv_invert_batched(b, A, X, d_info, BINV_F_SYNC, stream);
+}
+
+binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]) {
+  if (tier < 0 || tier >= kSmallTiers || shape < 0 || shape >= binv::small_variant_count(tier) || !out)
+    return bfail(BINV_E_INVALID, "tier or shape out of range");
+  int sh[4];
+  binv::small_variant_shape(tier, shape, sh);
+  for (int i = 0; i < 4; ++i) out[i] = sh[i];
   return BINV_OK;
 }
 

@@ -200,6 +200,7 @@ binv_status binv_create(binv_ctx** ctx, int device) {
   binv_ctx* c = new (std::nothrow) binv_ctx();
   if (!c) return fail(BINV_E_NOMEM, "out of host memory");
   c->device = device;
+  std::memset(c->tuned_small, -1, sizeof(c->tuned_small));
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->ncu = ncu;
@@ -300,11 +301,28 @@ binv_status residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, 
                           double* Res, hipStream_t s, double* rho) {
   HIP_TRY(binv::launch_gemm_f64(binv::kModeResid, A, lda, X, ldx, nullptr, 0, Res, n, n, s, nullptr));
   double* part = (double*)c->mx_part.p;
-  HIP_TRY(binv::launch_sumsq(Res, n, n, part, part + binv::kSumPartsHost, s));
+  HIP_TRY(binv::launch_sumsq(Res, n, n, n, part, part + binv::kSumPartsHost, s));
   double h = 0.0;
   HIP_TRY(hipMemcpyAsync(&h, part + binv::kSumPartsHost, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   *rho = std::sqrt(h / (double)n);
+  return BINV_OK;
+}
+
+// rho estimated from rows 0, t, 2t, ... (t = n / 64) of I - A X: the mean
+// squared row norm of the sample stands in for ||I - A X||_F^2 / n.
+constexpr int64_t kSampleRows = 64;
+binv_status sampled_residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X,
+                                  int64_t ldx, double* Res, hipStream_t s, double* rho) {
+  const int64_t rows = std::min<int64_t>(n, kSampleRows);
+  const int64_t stride = n / rows;
+  HIP_TRY(binv::launch_resid_rows(A, lda, X, ldx, Res, n, rows, stride, s));
+  double* part = (double*)c->mx_part.p;
+  HIP_TRY(binv::launch_sumsq(Res, n, rows, n, part, part + binv::kSumPartsHost, s));
+  double h = 0.0;
+  HIP_TRY(hipMemcpyAsync(&h, part + binv::kSumPartsHost, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *rho = std::sqrt(h / (double)rows);
   return BINV_OK;
 }
 
@@ -417,6 +435,7 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
   {
     const bool look = !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD));
     const bool from64 = opts && (opts->flags & BINV_F_REFINE_FROM_FP64);
+    const bool sampled = opts && (opts->flags & BINV_F_SAMPLED_CHECK);
     if (from64) {
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
@@ -426,6 +445,18 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     }
     if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
     if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
+    if (sampled) {
+      // accept the sweep on the sampled estimate when it already meets the target
+      double est = 0.0;
+      if ((st = sampled_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
+      if (est <= target) {
+        inf.rho_steps[0] = est;
+        inf.rho = est;
+        inf.sampled = 1;
+        inf.converged = 1;
+        goto out;
+      }
+    }
     if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
     if (!(rho < 0.5) && !from64) {
       // the FP32 sweep is too inaccurate for Newton-Schulz to converge: start
@@ -451,6 +482,17 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
       }
       inf.refine_steps = k + 1;
       const double prev_rho = rho;
+      if (sampled) {
+        double est = 0.0;
+        if ((st = sampled_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
+        if (est <= target) {
+          if (hk < 8) inf.rho_steps[hk++] = est;
+          inf.rho = est;
+          inf.sampled = 1;
+          inf.converged = 1;
+          goto out;
+        }
+      }
       if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
       if (hk < 8) inf.rho_steps[hk++] = rho;
       if (!(rho < prev_rho)) break;  // stagnated at the rounding floor (or diverging)

@@ -36,6 +36,7 @@ struct StepArgs {
   int region;
   int64_t tr0, tr1, tc0, tc1;
   int64_t ntiles;     // tiles enumerated by the region (before band skipping)
+  int64_t dstride;    // residual: output row i holds row i * dstride of I - A B
 };
 
 // One small matrix of a batch.
@@ -78,6 +79,8 @@ hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);
+hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int64_t ldx, double* R, int64_t n,
+                             int64_t rows, int64_t stride, hipStream_t s);
 constexpr int kModeResid = 2;  // C = I - A B
 constexpr int kModeAdd = 3;    // C = Cin + A B
 
@@ -92,12 +95,19 @@ hipError_t launch_row_panel_f32(const float* P, int64_t ldp, const float* W, int
                                 float* R, int64_t ldr, hipStream_t s);
 hipError_t launch_schur_f32(const float* Ct, int64_t ldc, const float* R, int64_t ldr, float* W, int64_t ldw, int64_t n,
                             int64_t o, int b, hipStream_t s);
-hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t n, double* part, double* out, hipStream_t s);
+hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t rows, int64_t cols, double* part, double* out,
+                        hipStream_t s);
 constexpr int kSumPartsHost = 1024;
 
 // batched.hip
+constexpr int kSmallVariants = 4;  // most launch shapes of a small tier (autotuned)
 hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                              int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s);
+hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, const SmallMat* mats,
+                             const int32_t* order, int64_t count, const int32_t* bounds, int32_t* info,
+                             hipStream_t s);
+void small_variant_shape(int tier, int variant, int shape[4]);
+int small_variant_count(int tier);
 int small_tier_limit(int tier);
 
 // binv_api.hip: records the thread-local message returned by binv_last_error
@@ -154,6 +164,9 @@ struct binv_ctx {
   // CUs) while the next pivot inversion runs on `side` (masked to the rest)
   hipStream_t side = nullptr, gemm = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
+  // autotuned launch shape of each small batched tier, by log2 of the
+  // tier's matrix count (-1: not tuned yet)
+  int8_t tuned_small[5][40];
   // mixed precision workspace
   binv::DevBuf mx_w32, mx_ct32, mx_r32, mx_p32, mx_p64a, mx_p64b, mx_res, mx_xn, mx_part;
   // optional per-phase event timing

@@ -27,6 +27,8 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <cstring>
+
 #include "binv_internal.h"
 
 namespace binv {
@@ -478,7 +480,7 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
       if (j >= g.N) continue;
       const bool jp = (j >= o && j < o + b);
       if (MODE == MODE_RESID) {
-        g.W[i * g.ldw + j] = (i == j ? 1.0 : 0.0) - acc[r][c];
+        g.W[i * g.ldw + j] = (i * g.dstride == j ? 1.0 : 0.0) - acc[r][c];
       } else if (MODE == MODE_ADD) {
         g.W[i * g.ldw + j] = g.Win[i * g.ldwin + j] + acc[r][c];
       } else if (MODE == MODE_ROW) {
@@ -696,8 +698,23 @@ hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double*
   g.Win = Cin; g.ldwin = ldcin;
   g.R = nullptr; g.ldr = 0;
   g.M = n; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
+  g.dstride = 1;
   if (mode == MODE_RESID) return launch_step<MODE_RESID, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
   return launch_step<MODE_ADD, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
+}
+
+// Rows 0, stride, 2 stride, ... (`rows` of them) of I - A X into R (rows x n,
+// ld = n): A's sampled rows are read with leading dimension lda * stride.
+hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int64_t ldx, double* R, int64_t n,
+                             int64_t rows, int64_t stride, hipStream_t s) {
+  StepArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda * stride;
+  g.B = X; g.ldb = ldx;
+  g.W = R; g.ldw = n;
+  g.M = rows; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
+  g.dstride = stride;
+  return launch_step<MODE_RESID, 64, 64, false>(g, s, 0, 0, 0, nullptr);
 }
 
 hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s) {

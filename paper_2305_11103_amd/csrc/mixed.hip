@@ -191,11 +191,11 @@ __global__ void __launch_bounds__(256, 2) k_gemm_step_f32(StepArgs32 g) {
 }
 
 // Deterministic sum of squares: fixed-size partials, then one final sum.
-__global__ void __launch_bounds__(256) k_sumsq_partial(const double* __restrict__ R, int64_t ldr, int64_t n,
-                                                       double* __restrict__ part) {
+__global__ void __launch_bounds__(256) k_sumsq_partial(const double* __restrict__ R, int64_t ldr, int64_t rows,
+                                                       int64_t n, double* __restrict__ part) {
   __shared__ double red[256];
   double acc = 0.0;
-  const int64_t total = n * n;
+  const int64_t total = rows * n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / n, j = e - i * n;
     const double x = R[i * ldr + j];
@@ -272,8 +272,9 @@ hipError_t launch_schur_f32(const float* Ct, int64_t ldc, const float* R, int64_
 }
 
 // out = sum of squares of the n x n matrix R (part: kSumParts doubles of scratch)
-hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t n, double* part, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sumsq_partial, dim3(kSumParts), dim3(256), 0, s, R, ldr, n, part);
+hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t rows, int64_t cols, double* part, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(kSumParts), dim3(256), 0, s, R, ldr, rows, cols, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, part, kSumParts, out);
   return hipGetLastError();
 }

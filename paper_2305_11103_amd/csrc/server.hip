@@ -21,6 +21,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -35,6 +36,7 @@ namespace {
 constexpr int kSmallMax = 128;     // orders batched into shared launches
 constexpr int kWorkers = 3;        // concurrent large requests
 constexpr int kMaxRoundSmall = 65536;
+constexpr double kFp32Reach = 1e-6;  // rho the FP32 sweep can meet without refinement
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -56,6 +58,8 @@ struct Request {
   double* dA = nullptr;       // device copy of A (server-owned)
   double* dX = nullptr;       // device result
   size_t bytes = 0;           // device bytes charged to the budget
+  bool on_device = false;     // dA/dX already allocated and charged at submit
+  bool fp32_start = false;    // the sweep ran in FP32 (mixed request)
   ReqState state = Q_QUEUED;
   binv_status status = BINV_OK;
   std::string error;
@@ -81,6 +85,7 @@ struct binv_server {
   int device = 0;
   size_t budget = 0;
   int max_inflight = 0;
+  uint32_t flags = 0;              // BINV_SERVER_*
   std::mutex mu;
   std::condition_variable cv;      // wakes the scheduler
   std::condition_variable wcv;     // wakes the workers
@@ -89,14 +94,25 @@ struct binv_server {
   std::vector<Request*> small_ready;
   std::unordered_map<uint64_t, Request*> all;
   size_t used = 0;
+  size_t peak = 0;
   int inflight = 0;
+  int large_running = 0;           // large requests on workers right now
   uint64_t next_id = 1;
   bool stop = false;
   std::thread sched;
   std::vector<std::thread> workers;
   binv_ctx* wctx[kWorkers] = {nullptr};
+  // Device blocks of finished requests, kept for reuse by size class so that
+  // collecting a result never calls hipFree (which waits for the whole
+  // device and would stall the other requests' work).
+  std::mutex pool_mu;
+  std::multimap<size_t, void*> pool;
+  size_t pooled = 0;
   // round buffers of the small-request path
   hipStream_t rstream = nullptr;
+  // copies in and out of request state; every copy is waited for, so a
+  // worker stream never reads a block before its input has landed
+  hipStream_t cstream = nullptr;
   binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo;
   // statistics
   std::atomic<int64_t> completed{0};
@@ -115,28 +131,108 @@ void finish(binv_server* s, Request* r, binv_status st, const std::string& err) 
   s->cv.notify_all();
 }
 
+hipError_t copy_sync(binv_server* s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s->cstream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->cstream);
+  return e;
+}
+
+// Allocation class of a request block: 1/8-octave steps, at least 64 KiB.
+size_t size_class(size_t bytes) {
+  size_t c = 64 << 10;
+  if (bytes <= c) return c;
+  int e = 63 - __builtin_clzll((unsigned long long)bytes);  // 2^e <= bytes < 2^(e+1)
+  const size_t step = (size_t)1 << (e - 3);
+  return (bytes + step - 1) / step * step;
+}
+
+void* pool_get(binv_server* s, size_t bytes) {
+  const size_t c = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> g(s->pool_mu);
+    auto it = s->pool.find(c);
+    if (it != s->pool.end()) {
+      void* p = it->second;
+      s->pool.erase(it);
+      s->pooled -= c;
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, c) == hipSuccess) return p;
+  (void)hipGetLastError();
+  // out of device memory: give the cached blocks back and try once more
+  std::multimap<size_t, void*> drop;
+  {
+    std::lock_guard<std::mutex> g(s->pool_mu);
+    drop.swap(s->pool);
+    s->pooled = 0;
+  }
+  for (auto& kv : drop) (void)hipFree(kv.second);
+  if (hipMalloc(&p, c) == hipSuccess) return p;
+  (void)hipGetLastError();
+  return nullptr;
+}
+
+// Return a block to the cache; the cache never holds more than the budget.
+void pool_put(binv_server* s, void* p, size_t bytes) {
+  if (!p) return;
+  const size_t c = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> g(s->pool_mu);
+    if (s->pooled + c <= s->budget) {
+      s->pool.emplace(c, p);
+      s->pooled += c;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+// A and X of one request share one block: A first, X after it.
+bool request_alloc(binv_server* s, Request* r) {
+  const size_t nn = std::max<size_t>((size_t)r->n * (size_t)r->n, 1);
+  double* p = (double*)pool_get(s, 2 * sizeof(double) * nn);
+  if (!p) return false;
+  r->dA = p;
+  r->dX = p + nn;
+  return true;
+}
+
+void request_release(binv_server* s, Request* r) {
+  if (r->dA) pool_put(s, r->dA, 2 * sizeof(double) * std::max<size_t>((size_t)r->n * (size_t)r->n, 1));
+  r->dA = r->dX = nullptr;
+}
+
 // Admit queued requests in order while memory and slots allow (mu held).
 void admit_locked(binv_server* s) {
   while (!s->queue.empty() && s->inflight < s->max_inflight) {
     Request* r = s->queue.front();
+    if (r->on_device) {
+      s->queue.pop_front();
+      s->inflight++;
+      r->state = Q_ADMITTED;
+      r->t_admit = now_s();
+      if (r->n <= kSmallMax) s->small_ready.push_back(r);
+      else {
+        s->large_ready.push_back(r);
+        s->wcv.notify_one();
+      }
+      continue;
+    }
     if (s->used + r->bytes > s->budget) break;  // wait until results are collected
     const size_t nn = (size_t)r->n * (size_t)r->n;
-    if (hipMalloc(&r->dA, sizeof(double) * std::max<size_t>(nn, 1)) != hipSuccess) {
-      r->dA = nullptr;
+    if (!request_alloc(s, r)) break;
+    if (copy_sync(s, r->dA, r->hostA.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipGetLastError();
+      request_release(s, r);
       break;
     }
-    if (hipMalloc(&r->dX, sizeof(double) * std::max<size_t>(nn, 1)) != hipSuccess) {
-      (void)hipFree(r->dA);
-      r->dA = nullptr;
-      r->dX = nullptr;
-      (void)hipGetLastError();
-      break;
-    }
-    if (nn) (void)hipMemcpy(r->dA, r->hostA.data(), sizeof(double) * nn, hipMemcpyHostToDevice);
     std::vector<double>().swap(r->hostA);
     s->queue.pop_front();
     s->used += r->bytes;
+    s->peak = std::max(s->peak, s->used);
     s->inflight++;
     r->state = Q_ADMITTED;
     r->t_admit = now_s();
@@ -215,6 +311,7 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
   for (int64_t i = 0; i < cnt; ++i) {
     std::memset(&reqs[i]->info, 0, sizeof(binv_info));
     reqs[i]->info.converged = 1;
+    reqs[i]->info.sampled = -1;  // Gauss-Jordan over the whole matrix; no residual formed
     if (e != BINV_OK) finish(s, reqs[i], e, err);
     else if (hinfo[i] != 0)
       finish(s, reqs[i], BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo[i]));
@@ -250,6 +347,7 @@ void worker_main(binv_server* s, int w) {
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   for (;;) {
     Request* r = nullptr;
+    bool alone = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->wcv.wait(lk, [&] { return s->stop || !s->large_ready.empty(); });
@@ -257,18 +355,32 @@ void worker_main(binv_server* s, int w) {
       r = s->large_ready.front();
       s->large_ready.pop_front();
       r->state = Q_RUNNING;
+      alone = s->large_running++ == 0;
     }
     binv_status e;
     std::memset(&r->info, 0, sizeof(binv_info));
     binv_opts o;
     std::memset(&o, 0, sizeof(o));
     o.block = r->n >= 2048 ? 512 : (r->n >= 512 ? 256 : 128);
-    o.flags = BINV_F_SYNC | (r->n < 4096 ? BINV_F_NO_LOOKAHEAD : 0u);
-    if (r->prec == BINV_PREC_MIXED_F32) {
-      e = binv_invert_mixed(s->wctx[w], r->n, r->dA, r->n, r->dX, r->n, &o, r->target, -1, st, &r->info);
-    } else {
-      e = binv_invert(s->wctx[w], r->n, r->dA, r->n, r->dX, r->n, &o, st, nullptr);
-      r->info.converged = 1;
+    // lookahead (a CU-masked side stream for the pivot chain) only pays when
+    // no other large request is there to fill the device meanwhile
+    o.flags = BINV_F_SYNC | ((r->n < 4096 || !alone) ? BINV_F_NO_LOOKAHEAD : 0u);
+    // Every request ends with the FP64 residual check against its target
+    // (sampled rows unless BINV_SERVER_FULL_CHECK) and is refined only if the
+    // check fails.  An FP64 request starts from the FP64 sweep.  A mixed
+    // request starts from the FP32 sweep when its target is within that
+    // sweep's reach or the server honours tags strictly; otherwise one
+    // Newton-Schulz step (two FP64 GEMMs of the sweep's size) would cost more
+    // than the FP64 sweep it saves, so it starts from the FP64 sweep too.
+    const bool fp32_start = r->prec == BINV_PREC_MIXED_F32 &&
+                            ((s->flags & BINV_SERVER_STRICT_PRECISION) || r->target >= kFp32Reach);
+    if (!fp32_start) o.flags |= BINV_F_REFINE_FROM_FP64;
+    if (!(s->flags & BINV_SERVER_FULL_CHECK)) o.flags |= BINV_F_SAMPLED_CHECK;
+    e = binv_invert_mixed(s->wctx[w], r->n, r->dA, r->n, r->dX, r->n, &o, r->target, -1, st, &r->info);
+    r->fp32_start = fp32_start;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      s->large_running--;
     }
     finish(s, r, e, e == BINV_OK ? "" : binv_last_error());
   }
@@ -279,7 +391,8 @@ void worker_main(binv_server* s, int w) {
 
 extern "C" {
 
-binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_inflight, binv_server** out) {
+binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_inflight, uint32_t flags,
+                               binv_server** out) {
   if (!out) return sfail(BINV_E_INVALID, "out is NULL");
   *out = nullptr;
   if (hbm_budget_bytes == 0) return sfail(BINV_E_INVALID, "zero HBM budget");
@@ -288,7 +401,10 @@ binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_
   s->device = device;
   s->budget = hbm_budget_bytes;
   s->max_inflight = max_inflight > 0 ? max_inflight : 1 << 20;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&s->rstream, hipStreamNonBlocking) != hipSuccess) {
+  s->flags = flags;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&s->rstream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess) {
+    if (s->rstream) (void)hipStreamDestroy(s->rstream);
     delete s;
     return sfail(BINV_E_HIP, "cannot use the device");
   }
@@ -297,6 +413,7 @@ binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_
     if (st != BINV_OK) {
       for (int v = 0; v < w; ++v) binv_destroy(s->wctx[v]);
       (void)hipStreamDestroy(s->rstream);
+      (void)hipStreamDestroy(s->cstream);
       delete s;
       return st;
     }
@@ -323,18 +440,45 @@ binv_status binv_submit(binv_server* s, int64_t n, const double* A, int a_is_dev
     return sfail(BINV_E_NOMEM, "request alone exceeds the server's HBM budget");
   }
   const size_t nn = (size_t)n * (size_t)n;
-  try {
-    r->hostA.resize(nn);
-  } catch (...) {
-    delete r;
-    return sfail(BINV_E_NOMEM, "out of host memory for staging");
+  if (a_is_device) {
+    // device input: copy it straight into the request's device state when the
+    // budget has room now (charged at once), else stage it in host memory
+    bool reserved = false;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      if (s->used + r->bytes <= s->budget) {
+        s->used += r->bytes;
+        s->peak = std::max(s->peak, s->used);
+        reserved = true;
+      }
+    }
+    if (reserved) {
+      hipError_t e = request_alloc(s, r) ? hipSuccess : hipErrorOutOfMemory;
+      if (e == hipSuccess) e = copy_sync(s, r->dA, A, sizeof(double) * nn, hipMemcpyDeviceToDevice);
+      if (e == hipSuccess) {
+        r->on_device = true;
+      } else {
+        (void)hipGetLastError();
+        request_release(s, r);
+        std::lock_guard<std::mutex> g(s->mu);
+        s->used -= r->bytes;
+      }
+    }
   }
-  hipError_t e = a_is_device ? hipMemcpy(r->hostA.data(), A, sizeof(double) * nn, hipMemcpyDeviceToHost)
-                             : hipSuccess;
-  if (!a_is_device) std::memcpy(r->hostA.data(), A, sizeof(double) * nn);
-  if (e != hipSuccess) {
-    delete r;
-    return sfail(BINV_E_HIP, std::string("copy of A: ") + hipGetErrorString(e));
+  if (!r->on_device) {
+    try {
+      r->hostA.resize(nn);
+    } catch (...) {
+      delete r;
+      return sfail(BINV_E_NOMEM, "out of host memory for staging");
+    }
+    hipError_t e = a_is_device ? copy_sync(s, r->hostA.data(), A, sizeof(double) * nn, hipMemcpyDeviceToHost)
+                               : hipSuccess;
+    if (!a_is_device) std::memcpy(r->hostA.data(), A, sizeof(double) * nn);
+    if (e != hipSuccess) {
+      delete r;
+      return sfail(BINV_E_HIP, std::string("copy of A: ") + hipGetErrorString(e));
+    }
   }
   r->t_submit = now_s();
   {
@@ -363,7 +507,7 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
   binv_status st = r->status;
   if (st == BINV_OK && X) {
     const size_t nn = (size_t)r->n * (size_t)r->n;
-    hipError_t e = hipMemcpy(X, r->dX, sizeof(double) * nn, x_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+    hipError_t e = copy_sync(s, X, r->dX, sizeof(double) * nn, x_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = sfail(BINV_E_HIP, std::string("copy of X: ") + hipGetErrorString(e));
   } else if (st != BINV_OK) {
     binv::set_error(r->error);
@@ -373,8 +517,7 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
     times->queue_ms = (r->t_admit - r->t_submit) * 1e3;
     times->total_ms = (r->t_done - r->t_submit) * 1e3;
   }
-  if (r->dA) (void)hipFree(r->dA);
-  if (r->dX) (void)hipFree(r->dX);
+  request_release(s, r);
   {
     std::lock_guard<std::mutex> g(s->mu);
     s->used -= r->bytes;
@@ -382,6 +525,15 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
   }
   delete r;
   return st;
+}
+
+binv_status binv_server_stats(binv_server* s, size_t* used, size_t* peak, int64_t* completed) {
+  if (!s) return sfail(BINV_E_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (used) *used = s->used;
+  if (peak) *peak = s->peak;
+  if (completed) *completed = s->completed.load();
+  return BINV_OK;
 }
 
 binv_status binv_server_destroy(binv_server* s) {
@@ -398,12 +550,13 @@ binv_status binv_server_destroy(binv_server* s) {
   for (auto& kv : s->all) {
     Request* r = kv.second;
     if (r->dA) (void)hipFree(r->dA);
-    if (r->dX) (void)hipFree(r->dX);
     delete r;
   }
+  for (auto& kv : s->pool) (void)hipFree(kv.second);
   for (int w = 0; w < kWorkers; ++w) binv_destroy(s->wctx[w]);
   for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo}) d->release();
   if (s->rstream) (void)hipStreamDestroy(s->rstream);
+  if (s->cstream) (void)hipStreamDestroy(s->cstream);
   delete s;
   return BINV_OK;
 }

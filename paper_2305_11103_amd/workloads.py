@@ -19,6 +19,10 @@ Workload recipes (all row-major float64):
                             down to 1/cond.
   spd_gram(m)               B B^T + 0.1 I with B Gaussian (small SPD matrices).
   spd_gram_batch(sizes)     the same for a whole uneven batch (PCG64 normals).
+  *_device variants         the same recipes formed on the GPU from PCG64
+                            draws (O'Neill 2014), for orders where the host QR
+                            is too slow: spd_haar_device, general_haar_device;
+                            householder_conditioned_device for request streams.
   near_equal_partition      floor(m/k) per block, remainder given one by one to
                             the last blocks (the convention of the paper's
                             Table 2 partition examples).
@@ -182,3 +186,71 @@ def spd_gram_batch(sizes, seed: int, shift: float = 0.1) -> list:
             G[np.diag_indices(m)] += shift
             out[i] = G
     return out
+
+
+def general_haar_device(n: int, seed: int, cond: float, device):
+    """general_haar on the GPU (torch): Gaussians from PCG64 on the host, QR
+    and the product on the device.  For orders where the host QR is too slow."""
+    import torch
+    g = np.random.Generator(np.random.PCG64(seed & 0xFFFFFFFFFFFFFFFF))
+    mats = []
+    for _ in range(2):
+        G = torch.from_numpy(g.standard_normal((n, n))).to(device)
+        Q, R = torch.linalg.qr(G)
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        mats.append(Q * d[None, :])
+        del G, R
+    U, V = mats
+    s = torch.from_numpy(geometric_singular_values(n, cond)).to(device)
+    return (U * s[None, :]) @ V.T.contiguous()
+
+
+def spd_haar_device(n: int, seed: int, cond: float, device):
+    """spd_haar's recipe on the GPU (torch): Q from the device QR of a PCG64
+    Gaussian (sign-fixed), s = 10^(log10(cond) u) with u from PCG64, s_0 = 1 and
+    s_1 = cond; symmetrised.  For orders where the host QR takes tens of seconds."""
+    import torch
+    g = np.random.Generator(np.random.PCG64(seed & 0xFFFFFFFFFFFFFFFF))
+    G = torch.from_numpy(g.standard_normal((n, n))).to(device)
+    Q, R = torch.linalg.qr(G)
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1.0
+    Q = Q * d[None, :]
+    del G, R
+    s = 10.0 ** (math.log10(cond) * g.random(n))
+    s[0] = 1.0
+    if n > 1:
+        s[1] = cond
+    A = (Q * torch.from_numpy(s).to(device)[None, :]) @ Q.T.contiguous()
+    return 0.5 * (A + A.T)
+
+
+def request_stream(count: int, seed: int, lo: int = 5, hi: int = 8192):
+    """Order n = round(exp(U[ln lo, ln hi])), condition 10^U[1, 6] and a
+    precision tag (fp64 or mixed, probability 1/2) for each request."""
+    u = uniform(seed, 3 * count)
+    n = np.rint(np.exp(np.log(lo) + u[:count] * (np.log(hi) - np.log(lo)))).astype(np.int64)
+    cond = 10.0 ** (1.0 + 5.0 * u[count:2 * count])
+    tag = np.where(u[2 * count:] < 0.5, "fp64", "mixed")
+    return n, cond, tag
+
+
+def householder_conditioned_device(n: int, seed: int, cond: float, device, reflectors: int = 4):
+    """U diag(pi(s)) V^T with U and V each a product of `reflectors` random
+    Householder reflectors and pi a random permutation of geometric singular
+    values from 1 to 1/cond (so the condition number is exactly cond), formed
+    on the device in O(n^2) work."""
+    import torch
+    g = np.random.Generator(np.random.PCG64(seed & 0xFFFFFFFFFFFFFFFF))
+    s = geometric_singular_values(n, cond)[g.permutation(n)]
+    A = torch.diag(torch.from_numpy(s).to(device))
+    for side in (0, 1):
+        for _ in range(reflectors):
+            v = torch.from_numpy(g.standard_normal(n)).to(device)
+            v = v / torch.linalg.vector_norm(v)
+            if side == 0:
+                A -= 2.0 * torch.outer(v, v @ A)
+            else:
+                A -= 2.0 * torch.outer(A @ v, v)
+    return A

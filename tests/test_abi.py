@@ -40,3 +40,16 @@ def test_version_string():
     from paper_2305_11103_amd import binv
     lib = binv.load_library()
     assert lib.binv_version().decode().startswith("binv")
+
+
+def test_tier_shape_table():
+    """Launch-shape table of the batched tiers (host-only query)."""
+    from paper_2305_11103_amd import binv
+    for t, count in enumerate(binv.TIER_SHAPES):
+        for v in range(count):
+            rpl, cpw, nwv, sub = binv.batch_shape(t, v)
+            limit = (8, 16, 32, 64, 128)[t]
+            assert nwv * cpw >= limit and nwv * cpw <= 64 * rpl  # columns cover the tier, rows cover the columns
+            assert 64 * nwv * sub <= 1024
+        with pytest.raises(binv.BinvError):
+            binv.batch_shape(t, count)

@@ -129,3 +129,39 @@ def test_invalid_plans_rejected(gpu):
         binv.Batch([300])
     with pytest.raises(binv.BinvError):
         binv.Batch([5], parts=[[2, 2]])
+
+
+def test_autotuned_shapes_are_bitwise_equal_to_default(gpu):
+    """Every launch shape of a tier runs the same arithmetic: the tuned plan's
+    result equals the default plan's bit for bit, for every tier."""
+    import torch
+    from paper_2305_11103_amd import binv
+    sizes = [5] * 300 + [12] * 40 + [30] * 40 + [60] * 30 + [120] * 20 + [200] * 5
+    rng = np.random.default_rng(9)
+    mats = [wl.spd_gram(m, 400 + i) for i, m in enumerate(sizes)]
+    ks = [int(rng.integers(2, 5)) for _ in sizes]
+    ctx = binv.Context(0)  # fresh context: no remembered choices
+    ref_plan = binv.Batch(sizes, ks=ks, ctx=ctx)
+    A = torch.from_numpy(ref_plan.pack(mats)).cuda()
+    X0, info0 = ref_plan.invert(A, graph=False)
+    X0 = X0.clone()
+    plan = binv.Batch(sizes, ks=ks, ctx=ctx)
+    X = torch.empty_like(A)
+    chosen, ms, shapes = plan.tune(A, X, reps=2)
+    assert all(0 <= c < len(shapes[t]) for t, c in enumerate(chosen))
+    for t in range(5):
+        assert all(v > 0 for v in ms[t])
+    torch.cuda.synchronize()
+    assert torch.equal(X, X0)  # the tuner leaves a complete inversion behind
+    for graph in (False, True):
+        X2, info2 = plan.invert(A, graph=graph)
+        torch.cuda.synchronize()
+        assert torch.equal(X2, X0)
+        assert torch.equal(info2, info0)
+    # a later plan on the same context starts from the remembered choice
+    later = binv.Batch(sizes, ks=ks, ctx=ctx)
+    X3, _ = later.invert(A, graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(X3, X0)
+    for A_, Xi in zip(mats[::37], plan.unpack(X0.cpu().numpy())[::37]):
+        check(A_, Xi, 1e-12)

@@ -74,3 +74,35 @@ def test_mixed_singular(gpu):
     A = np.eye(64)[::-1].copy()
     with pytest.raises(binv.SingularError):
         run(A, block=32)
+
+
+def test_sampled_check_accepts_an_accurate_sweep(gpu):
+    """BINV_F_SAMPLED_CHECK: an FP64 sweep that already meets the target is
+    accepted on the 64-row estimate (no refinement, X bitwise equal to the
+    plain sweep), and the estimate tracks the oracle's full residual."""
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 640
+    A = wl.spd_haar(n, 77, 1e3)
+    At = torch.from_numpy(A).cuda()
+    X, info = binv.invert_mixed(At, block=128, from_fp64=True, sampled_check=True)
+    Xp = binv.invert(At, block=128)
+    torch.cuda.synchronize()
+    assert info["sampled"] == 1 and info["refine_steps"] == 0 and info["converged"]
+    assert torch.equal(X, Xp)
+    full = oracle.residual_stats(A, X.cpu().numpy())["rho"]
+    assert full / 4 <= info["rho"] <= 4 * full
+
+
+def test_sampled_check_refines_when_the_sweep_misses(gpu):
+    """A start that misses the target is refined; the final iterate meets the
+    target by the oracle's full residual."""
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 768
+    A = wl.general_haar(n, 78, 1e2)
+    At = torch.from_numpy(A).cuda()
+    X, info = binv.invert_mixed(At, block=128, sampled_check=True)
+    torch.cuda.synchronize()
+    assert info["refine_steps"] >= 1 and info["converged"]
+    assert oracle.residual_stats(A, X.cpu().numpy())["rho"] <= 1e-10

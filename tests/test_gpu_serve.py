@@ -1,0 +1,114 @@
+"""Continuous-batching server (GPU): every result is the same alone and in the
+mix, meets its accuracy target (oracle residual), and admission never holds
+more device memory than the budget."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11103_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def wait_all(srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            try:
+                r = srv.poll(t)
+            except Exception as e:  # failed request: keep the exception
+                out[t] = e
+                continue
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError("requests did not finish")
+        time.sleep(0.002)
+    return out
+
+
+def alone(A, n, prec, strict=True, full_check=True):
+    """The same request through the single-matrix entry points, under the
+    server's policy: FP64 start unless a mixed request is honoured strictly
+    (its target 1e-10 is below the FP32 sweep's reach)."""
+    import torch
+    from paper_2305_11103_amd import binv
+    At = torch.from_numpy(A).cuda()
+    if n <= 128:
+        b = binv.Batch([n])
+        X, _ = b.invert(At.reshape(-1).contiguous(), graph=False)
+        return X.reshape(n, n).cpu().numpy()
+    blk = 512 if n >= 2048 else (256 if n >= 512 else 128)
+    X, _ = binv.invert_mixed(At, block=blk, lookahead=n >= 4096, from_fp64=prec == "fp64" or not strict,
+                             sampled_check=not full_check)
+    return X.cpu().numpy()
+
+
+@pytest.mark.parametrize("strict,full_check", [(True, True), (False, False)])
+def test_mix_matches_alone_bitwise_and_meets_target(gpu, strict, full_check):
+    import torch
+    from paper_2305_11103_amd import binv
+    srv = binv.Server(hbm_budget=8 << 30, strict_precision=strict, full_check=full_check)
+    sizes = [5, 7, 16, 33, 64, 100, 128, 129, 200, 513, 700, 1100, 2048]
+    reqs = []
+    for i, n in enumerate(sizes * 2):
+        prec = "mixed" if (i % 2 and n > 128) else "fp64"
+        A = wl.spd_gram(n, 1000 + i) if n <= 256 else wl.general_haar(n, 2000 + i, 1e3) if prec == "mixed" \
+            else wl.spd_haar(n, 2000 + i, 1e3)
+        # every third request comes from device memory (copied at once)
+        src = torch.from_numpy(A).cuda() if i % 3 == 0 else A
+        torch.cuda.synchronize()
+        reqs.append((A, n, prec, srv.submit(src, prec=prec)))
+        del src
+    res = wait_all(srv, [r[3] for r in reqs])
+    for A, n, prec, t in reqs:
+        X, info, times = res[t]
+        assert info["converged"]
+        assert times["total_ms"] >= times["queue_ms"] >= 0
+        assert np.array_equal(X, alone(A, n, prec, strict, full_check)), (n, prec)
+        assert info["sampled"] == (-1 if n <= 128 else (0 if full_check else info["sampled"]))
+        assert oracle.residual_stats(A, X)["rho"] <= 1e-10
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["used"] == 0 and st["peak"] <= 8 << 30
+    srv.close()
+
+
+def test_admission_holds_at_most_the_budget(gpu):
+    from paper_2305_11103_amd import binv
+    n = 1024
+    budget = 3 * (16 * n * n + 4 * 8 * 512 * n + 8 * 512 * 512 * 2)  # room for three requests
+    srv = binv.Server(hbm_budget=budget)
+    mats = [wl.spd_haar(n, 70 + i, 1e2) for i in range(8)]
+    tickets = [srv.submit(A) for A in mats]
+    res = wait_all(srv, tickets)
+    assert srv.stats()["peak"] <= budget
+    for A, t in zip(mats, tickets):
+        assert oracle.residual_stats(A, res[t][0])["rho"] <= 1e-10
+    srv.close()
+
+
+def test_singular_request_fails_alone(gpu):
+    from paper_2305_11103_amd import binv
+    srv = binv.Server(hbm_budget=1 << 30)
+    good = wl.spd_gram(50, 3)
+    bad = np.eye(300)[::-1].copy()
+    tg, tb = srv.submit(good), srv.submit(bad)
+    res = wait_all(srv, [tg, tb])
+    assert isinstance(res[tb], binv.SingularError)
+    assert oracle.residual_stats(good, res[tg][0])["rho"] <= 1e-12
+    srv.close()
+
+
+def test_budget_and_ticket_errors(gpu):
+    from paper_2305_11103_amd import binv
+    srv = binv.Server(hbm_budget=1 << 20)
+    with pytest.raises(binv.BinvError):
+        srv.submit(np.eye(1000))
+    with pytest.raises(binv.BinvError):
+        srv.poll(12345)
+    srv.close()
