@@ -137,8 +137,7 @@ typedef struct {
                               as the starting point */
   int32_t converged;       /* 1: rho <= target */
   int32_t sampled;         /* 1: rho is the sampled-rows estimate
-                              (BINV_F_SAMPLED_CHECK); -1: no residual was
-                              formed (rho = 0) */
+                              (BINV_F_SAMPLED_CHECK); 0: the full residual */
 } binv_info;
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
@@ -207,6 +206,12 @@ binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, in
 binv_status binv_batch_tune(binv_batch* plan, const double* A, double* X, int32_t* d_info, int32_t reps,
                             void* stream, int32_t* chosen, double* ms);
 
+/* rho_i = ||A_i X_i - I||_F / sqrt(m_i) of every matrix of the plan, computed
+ * in FP64 on the device (one workgroup per matrix, 2 m_i^3 flops) into
+ * d_rho[i] (device double[count]).  Stream-ordered; A and X as for
+ * binv_invert_batched. */
+binv_status binv_batch_residual(binv_batch* plan, const double* A, const double* X, double* d_rho, void* stream);
+
 /* Launch shape of (tier, shape index): {rows per lane, columns per wave,
  * waves per matrix, matrices per workgroup}.  BINV_E_INVALID for an index the
  * tier does not have. */
@@ -233,8 +238,10 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
  * fails.  BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
  * the FP32 sweep under the policy of BINV_SERVER_STRICT_PRECISION below.
- * Requests of order <= 128 are always FP64 Gauss-Jordan and carry no
- * residual check (info->sampled = -1, rho = 0).
+ * Requests of order <= 128 are inverted in FP64 (Gauss-Jordan with pivoting
+ * over the whole matrix, shared launches), then checked on their full
+ * residual and refined by up to three Newton-Schulz steps where they miss
+ * their target (info->sampled = 0).
  * binv_poll returns BINV_E_BUSY until the request is done; then it copies X
  * (n x n row-major, host or device pointer, may be NULL), fills *info and
  * *times (either may be NULL), releases the request's device memory and

@@ -30,7 +30,7 @@ BINV_F_NO_LOOKAHEAD = 2
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
            "binv_invert_mixed",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
-           "binv_batch_tune", "binv_batch_shape",
+           "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
            "binv_server_create", "binv_submit", "binv_poll", "binv_server_stats", "binv_server_destroy",
            "binv_last_error", "binv_version")
 BINV_F_GRAPH = 4
@@ -127,6 +127,8 @@ def load_library():
     lib.binv_batch_tune.restype = ctypes.c_int
     lib.binv_batch_shape.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.binv_batch_shape.restype = ctypes.c_int
+    lib.binv_batch_residual.argtypes = [P, P, P, P, P]
+    lib.binv_batch_residual.restype = ctypes.c_int
     lib.binv_last_error.argtypes = []
     lib.binv_last_error.restype = ctypes.c_char_p
     lib.binv_version.argtypes = []
@@ -370,6 +372,16 @@ class Batch:
                                                   int(reps), _stream_handle(torch, A.device.index or 0), chosen, ms))
         return list(chosen), [list(ms[4 * t:4 * t + TIER_SHAPES[t]]) for t in range(5)], [
             [batch_shape(t, v) for v in range(TIER_SHAPES[t])] for t in range(5)]
+
+    def residual(self, A, X):
+        """rho_i = ||A_i X_i - I||_F / sqrt(m_i) for every matrix (float64 CUDA tensor)."""
+        import torch
+        rho = torch.empty(max(self.count, 1), dtype=torch.float64, device=A.device)
+        with torch.cuda.device(A.device):
+            _check(load_library().binv_batch_residual(self._h, ctypes.c_void_p(A.data_ptr()),
+                                                      ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                                      _stream_handle(torch, A.device.index or 0)))
+        return rho[: self.count]
 
     def pack(self, mats):
         """Pack a list of square numpy matrices into one flat float64 array."""

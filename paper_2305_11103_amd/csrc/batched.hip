@@ -36,6 +36,45 @@ __device__ __forceinline__ double bread_f64(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Pivot search of one column x[h] (row lane + 64 h) among the rows of [bs, be)
+// not used yet: key = bits(|x|) + 1 orders like |x| (0 excludes a row), one
+// 64-bit wave max as two 32-bit DPP reductions, lowest row on ties.  With
+// `publish` the wave stores the multipliers and the pivot into the LDS slot.
+template <int RPL>
+__device__ __forceinline__ void small_search(const double (&x)[RPL], const bool (&used)[RPL], int bs, int be,
+                                             bool publish, double* colbuf, int* s_r, double* s_pv, int lane) {
+  unsigned long long key[RPL];
+  unsigned long long kmax = 0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int row = lane + 64 * h;
+    const bool cand = !used[h] && row >= bs && row < be;
+    key[h] = cand ? (unsigned long long)__double_as_longlong(fabs(x[h])) + 1ULL : 0ULL;
+    kmax = key[h] > kmax ? key[h] : kmax;
+  }
+  const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
+  const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
+  kmax = ((unsigned long long)hi << 32) | lo;
+  int r = 64 * RPL;
+#pragma unroll
+  for (int h = RPL - 1; h >= 0; --h) {
+    const unsigned long long mk = __ballot(key[h] == kmax);
+    if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
+  }
+  double pv = 0.0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h)
+    if ((r >> 6) == h) pv = bread_f64(x[h], r & 63);
+  if (publish) {
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) colbuf[lane + 64 * h] = x[h];
+    if (lane == 0) {
+      *s_r = r;
+      *s_pv = pv;
+    }
+  }
+}
+
 template <int RPL, int CPW, int NWV, int SUB>
 __global__ void __launch_bounds__(64 * NWV * SUB)
 k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const SmallMat* __restrict__ mats,
@@ -78,10 +117,17 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
     }
   }
 
-  // current diagonal block [bs, be) of the column being eliminated
+  // current diagonal block [bs, be) of the column being eliminated (the
+  // padding beyond m forms a last block of its own)
   int blk = 0;
   int bs = 0;
   int be = (mt.nb > 0) ? bounds[mt.bnd + 1] : NB;
+  {
+    double x[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) x[h] = v[h][0];
+    small_search<RPL>(x, used, bs, be, wave == 0, colbuf[sub][0], &s_r[sub][0], &s_pv[sub][0], lane);
+  }
   bool singular = false;
   for (int cw = 0; cw < NWV; ++cw) {
     const bool owner = (wave == cw);
@@ -89,41 +135,6 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
     for (int t = 0; t < CPW; ++t) {
       const int c = cw * CPW + t;
       const int buf = c & 1;
-      if (c == be) {  // uniform: advance to the next diagonal block (or padding)
-        bs = be;
-        ++blk;
-        be = (blk < mt.nb) ? bounds[mt.bnd + blk + 1] : NB;
-      }
-      if (owner) {
-        unsigned long long key[RPL];
-        unsigned long long kmax = 0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          const int row = lane + 64 * h;
-          const bool cand = !used[h] && row >= bs && row < be;
-          key[h] = cand ? (unsigned long long)__double_as_longlong(fabs(v[h][t])) + 1ULL : 0ULL;
-          kmax = key[h] > kmax ? key[h] : kmax;
-        }
-        const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
-        const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
-        kmax = ((unsigned long long)hi << 32) | lo;
-        int r = 64 * RPL;
-#pragma unroll
-        for (int h = RPL - 1; h >= 0; --h) {
-          const unsigned long long mk = __ballot(key[h] == kmax);
-          if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
-        }
-        double pv = 0.0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          colbuf[sub][buf][lane + 64 * h] = v[h][t];
-          if ((r >> 6) == h) pv = bread_f64(v[h][t], r & 63);
-        }
-        if (lane == 0) {
-          s_r[sub][buf] = r;
-          s_pv[sub][buf] = pv;
-        }
-      }
       __syncthreads();
       const int r = s_r[sub][buf];
       const double pv = s_pv[sub][buf];
@@ -143,17 +154,40 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
         for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[RPL - 1][j], rl) * q;
       }
       sp[t] = owner ? q : sp[t];
+      double f[RPL];
 #pragma unroll
       for (int h = 0; h < RPL; ++h) {
         const int row = lane + 64 * h;
         const bool isr = (row == r);
-        const double f = isr ? 0.0 : colbuf[sub][buf][row];
+        f[h] = isr ? 0.0 : colbuf[sub][buf][row];
         v[h][t] = owner ? (isr ? 1.0 : 0.0) : v[h][t];
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) v[h][j] = fma(-f, sp[j], v[h][j]);
         used[h] = used[h] || isr;
         step_of[h] = isr ? c : step_of[h];
         scale[h] = isr ? q : scale[h];
+      }
+      // the block of column c + 1 (uniform)
+      if (c + 1 == be) {
+        bs = be;
+        ++blk;
+        be = (blk < mt.nb) ? bounds[mt.bnd + blk + 1] : NB;
+      }
+      // column c + 1 first (slot s of wave (c + 1) / CPW), then its search
+      const int s = (t + 1) % CPW;  // a constant once the t loop is unrolled
+      const bool next_owner = (t + 1 < CPW) ? owner : (wave == cw + 1);
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) v[h][s] = fma(-f[h], sp[s], v[h][s]);
+      if (c + 1 < NB && next_owner) {
+        double x[RPL];
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) x[h] = v[h][s];
+        small_search<RPL>(x, used, bs, be, true, colbuf[sub][buf ^ 1], &s_r[sub][buf ^ 1], &s_pv[sub][buf ^ 1],
+                          lane);
+      }
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+          if (j != s) v[h][j] = fma(-f[h], sp[j], v[h][j]);
       }
       if (wave == 0 && lane == 0) piv_row[sub][c] = r;
     }
@@ -174,6 +208,130 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
       if (col < m) dst[piv_row[sub][col]] = v[h][j] * scale[h];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Residual and Newton-Schulz refinement of small matrices (one workgroup per
+// matrix): R = I - A X and rho = ||R||_F / sqrt(m); while rho > target (at
+// most max_steps times) X <- X + X R and R, rho again; a step that does not
+// lower rho ends the loop.  Products are 64 x 64 output tiles over 16-deep
+// LDS chunks, each thread owning a 4 x 4 block.
+// ---------------------------------------------------------------------------
+constexpr int kRefThreads = 256;
+
+// Out = I - L M (MODE 0; also returns sum Out^2 over the workgroup) or
+// Out = Add + L M (MODE 1); all m x m row-major, ld = m.  Out may be NULL in
+// MODE 0 (norm only).
+template <int MODE>
+__device__ double small_product(const double* __restrict__ L, const double* __restrict__ M,
+                                const double* __restrict__ Add, double* __restrict__ Out, int m, double* red) {
+  __shared__ double Ls[64][17];
+  __shared__ double Ms[16][65];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const int tiles = (m + 63) / 64;
+  double ss = 0.0;
+  for (int tile = 0; tile < tiles * tiles; ++tile) {
+    const int i0 = (tile / tiles) * 64, j0 = (tile % tiles) * 64;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = tid + e * kRefThreads;  // 0..1023
+        const int li = idx >> 4, lk = idx & 15;
+        Ls[li][lk] = (i0 + li < m && k0 + lk < m) ? L[(int64_t)(i0 + li) * m + k0 + lk] : 0.0;
+        const int mk = idx >> 6, mj = idx & 63;
+        Ms[mk][mj] = (k0 + mk < m && j0 + mj < m) ? M[(int64_t)(k0 + mk) * m + j0 + mj] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        double lv[4], mv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) lv[a] = Ls[ty * 4 + a][kk];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) mv[b] = Ms[kk][tx * 4 + b];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(lv[a], mv[b], acc[a][b]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + ty * 4 + a;
+      if (i >= m) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = j0 + tx * 4 + b;
+        if (j >= m) continue;
+        if (MODE == 0) {
+          const double r = (i == j ? 1.0 : 0.0) - acc[a][b];
+          ss = fma(r, r, ss);
+          if (Out) Out[(int64_t)i * m + j] = r;
+        } else {
+          Out[(int64_t)i * m + j] = Add[(int64_t)i * m + j] + acc[a][b];
+        }
+      }
+    }
+  }
+  // workgroup sum (fixed order: deterministic)
+  red[tid] = ss;
+  __syncthreads();
+  for (int w = kRefThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double tot = red[0];
+  __syncthreads();
+  return tot;
+}
+
+// Matrix `i` of the list: A, X at mats[idx].off (ld = m); work holds 2 m^2
+// doubles per matrix at 2 * off (refinement only).  rho[id], steps[id]
+// (either may be NULL) receive the final rho and the number of steps.
+__global__ void __launch_bounds__(kRefThreads)
+k_small_refine(const double* __restrict__ A, double* __restrict__ X, const SmallMat* __restrict__ mats,
+               const int32_t* __restrict__ order, double* __restrict__ work, double target,
+               const double* __restrict__ targets, int max_steps, double* __restrict__ rho,
+               int32_t* __restrict__ steps) {
+  __shared__ double red[kRefThreads];
+  const SmallMat mt = mats[order ? order[blockIdx.x] : blockIdx.x];
+  const int m = mt.m;
+  const double tgt = targets ? targets[mt.id] : target;
+  const double* a = A + mt.off;
+  double* x = X + mt.off;
+  double* R = work ? work + 2 * mt.off : nullptr;
+  double* Xn = R ? R + (int64_t)m * m : nullptr;
+  double r = sqrt(small_product<0>(a, x, nullptr, R, m, red) / m);
+  int k = 0;
+  for (; R && k < max_steps && r > tgt; ++k) {
+    small_product<1>(x, R, x, Xn, m, red);  // Xn = X + X R
+    __syncthreads();
+    const double rn = sqrt(small_product<0>(a, Xn, nullptr, R, m, red) / m);  // R of Xn
+    if (!(rn < r)) break;  // rounding floor: keep X
+    for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += kRefThreads) x[e] = Xn[e];
+    __syncthreads();
+    r = rn;
+  }
+  if (threadIdx.x == 0) {
+    if (rho) rho[mt.id] = r;
+    if (steps) steps[mt.id] = k;
+  }
+}
+
+hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats, const int32_t* order, int64_t count,
+                               double* work, double target, const double* targets, int max_steps, double* rho,
+                               int32_t* steps, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_small_refine, dim3((unsigned)count), dim3(kRefThreads), 0, s, A, X, mats, order, work, target,
+                     targets, max_steps, rho, steps);
+  return hipGetLastError();
 }
 
 // Launch shapes of the register kernel, per tier.  Every shape runs the same

@@ -471,6 +471,16 @@ binv_status binv_batch_tune(binv_batch* b, const double* A, double* X, int32_t* 
   return binv_invert_batched(b, A, X, d_info, BINV_F_SYNC, stream);
 }
 
+binv_status binv_batch_residual(binv_batch* b, const double* A, const double* X, double* d_rho, void* stream) {
+  if (!b) return bfail(BINV_E_INVALID, "plan is NULL");
+  if (b->count == 0) return BINV_OK;
+  if (!A || !X || !d_rho) return bfail(BINV_E_INVALID, "A, X and d_rho must be device pointers");
+  // norm only: X is read, never written (no workspace)
+  BHIP(binv::launch_small_refine(A, const_cast<double*>(X), (const binv::SmallMat*)b->d_mats, nullptr, b->count,
+                                 nullptr, 0.0, nullptr, 0, d_rho, nullptr, (hipStream_t)stream));
+  return BINV_OK;
+}
+
 binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]) {
   if (tier < 0 || tier >= kSmallTiers || shape < 0 || shape >= binv::small_variant_count(tier) || !out)
     return bfail(BINV_E_INVALID, "tier or shape out of range");

@@ -8,6 +8,8 @@
 // same block sweep on a private copy with 64-wide sub-blocks.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -95,12 +97,31 @@ binv_status ensure_side(binv_ctx* c) {
   if (c->side) return BINV_OK;
   const int words = (c->ncu + 31) / 32;
   std::vector<uint32_t> mg(words, 0u), ms(words, 0u);
+  // Workgroups are dealt to the 8 XCDs round-robin whatever the mask, so the
+  // reserved CUs must be spread evenly over the XCDs, or the XCD that lost
+  // them becomes the straggler of every trailing update.  The mask's bits run
+  // XCD by XCD (measured: reserving the last bit of each eighth of the mask
+  // keeps the trailing update at 47.8 TFLOP/s, reserving the last 8 bits drops
+  // it to 42.6), so the reserved CUs are the last ones of each eighth.
+  // BINV_SIDE_NCU overrides how many CUs are reserved (a multiple of 8).
+  static const int nres = [] {
+    const char* e = getenv("BINV_SIDE_NCU");
+    const int v = e ? atoi(e) : kReserveCUs;
+    return (v >= 8 && v <= 64) ? v / 8 * 8 : kReserveCUs;
+  }();
+  std::vector<char> reserved(c->ncu, 0);
+  const int span = std::max(1, c->ncu / 8);
+  for (int x = 0; x < 8; ++x)
+    for (int r = 0; r < nres / 8; ++r) {
+      const int cu = (x + 1) * span - 1 - r;
+      if (cu >= 0 && cu < c->ncu) reserved[cu] = 1;
+    }
   for (int cu = 0; cu < c->ncu; ++cu) {
-    if (cu < c->ncu - kReserveCUs) mg[cu / 32] |= 1u << (cu % 32);
+    if (!reserved[cu]) mg[cu / 32] |= 1u << (cu % 32);
     else ms[cu / 32] |= 1u << (cu % 32);
   }
   // CU-masked streams; plain streams if masking is unavailable
-  if (c->ncu <= 2 * kReserveCUs ||
+  if (c->ncu <= 2 * nres ||
       hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) != hipSuccess ||
       hipExtStreamCreateWithCUMask(&c->side, (uint32_t)words, ms.data()) != hipSuccess) {
     if (c->gemm) (void)hipStreamDestroy(c->gemm);

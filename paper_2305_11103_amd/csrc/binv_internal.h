@@ -109,6 +109,12 @@ hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, 
 void small_variant_shape(int tier, int variant, int shape[4]);
 int small_variant_count(int tier);
 int small_tier_limit(int tier);
+// Residual (and optional Newton-Schulz refinement) of packed small matrices:
+// one workgroup per listed matrix; work = 2 m^2 doubles per matrix at 2 * off
+// (NULL: residual norm only); targets[id] (or `target` when NULL) per matrix.
+hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats, const int32_t* order, int64_t count,
+                               double* work, double target, const double* targets, int max_steps, double* rho,
+                               int32_t* steps, hipStream_t s);
 
 // binv_api.hip: records the thread-local message returned by binv_last_error
 void set_error(const std::string& msg);

@@ -66,6 +66,53 @@ __device__ __forceinline__ void record_singular(long long* info, long long row) 
 }
 __device__ __forceinline__ void record_singular(int* info, long long row) { atomicCAS(info, 0, (int)row); }
 
+// Pivot search of one column held as x[h] (row lane + 64 h) in every lane of
+// a wave: for non-negative doubles the IEEE bit pattern orders like the value,
+// so key = bits(|x|) + 1 (0 for rows already used) turns the search into one
+// integer wave-max (two 32-bit DPP reductions); ties go to the lowest row.
+// With `publish` the wave stores the column of multipliers and the pivot
+// (row, value) into the LDS slot.
+template <int RPL>
+__device__ __forceinline__ void leaf_search(const double (&x)[RPL], const bool (&used)[RPL], bool publish,
+                                            double* colbuf, int* s_r, double* s_pv, int lane) {
+  unsigned long long key[RPL];
+  unsigned long long kmax = 0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    key[h] = used[h] ? 0ULL : (unsigned long long)__double_as_longlong(fabs(x[h])) + 1ULL;
+    kmax = key[h] > kmax ? key[h] : kmax;
+  }
+  const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
+  const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
+  kmax = ((unsigned long long)hi << 32) | lo;
+  int r = 64 * RPL;
+#pragma unroll
+  for (int h = RPL - 1; h >= 0; --h) {
+    const unsigned long long mk = __ballot(key[h] == kmax);
+    if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
+  }
+  double pv = 0.0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h)
+    if ((r >> 6) == h) pv = readlane_f64(x[h], r & 63);
+  if (publish) {
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) colbuf[lane + 64 * h] = x[h];
+    if (lane == 0) {
+      *s_r = r;
+      *s_pv = pv;
+    }
+  }
+}
+
+// Rows are stored unscaled: when row r becomes the pivot of column c (value
+// pv, q = 1/pv) its stored values stay, its column-c slot becomes 1 and its
+// scale q.  A later update of any row subtracts (its stored multiplier) x
+// (the true, scaled pivot row), which is the true update divided by that
+// row's scale, so each element costs one fma per column and every row is
+// rescaled once at the end.  The pivot of column c + 1 is searched as soon as
+// that column has been updated for column c, before the rest of the update,
+// so the search overlaps the other waves' work instead of following it.
 template <int RPL, int CPW, int NWV, class InfoT>
 __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t lda, double* __restrict__ P,
                                           int64_t ldp, int b, int64_t row0, InfoT* info) {
@@ -83,6 +130,7 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
 
   // diag(A, I) has inverse diag(A^-1, I): padding keeps the loop uniform.
   double v[RPL][CPW];
+  double scale[RPL];
   bool used[RPL];
   int step_of[RPL];
 #pragma unroll
@@ -90,11 +138,18 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
     const int row = lane + 64 * h;
     used[h] = row >= NB;  // rows beyond the padded block never pivot
     step_of[h] = 0;
+    scale[h] = 1.0;
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int col = cbase + j;
       v[h][j] = (row < b && col < b) ? A[(int64_t)row * lda + col] : (row == col ? 1.0 : 0.0);
     }
+  }
+  {
+    double x[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) x[h] = v[h][0];
+    leaf_search<RPL>(x, used, wave == 0, colbuf[0], &s_r[0], &s_pv[0], lane);
   }
 
   bool singular = false;
@@ -104,40 +159,6 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
     for (int t = 0; t < CPW; ++t) {
       const int c = cw * CPW + t;
       const int buf = c & 1;
-      if (owner) {
-        // Pivot search.  For non-negative doubles the IEEE bit pattern orders
-        // like the value, so key = bits(|v|) + 1 (0 for rows already used)
-        // turns the search into one integer wave-max; ties go to the lowest row.
-        unsigned long long key[RPL];
-        unsigned long long kmax = 0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          key[h] = used[h] ? 0ULL : (unsigned long long)__double_as_longlong(fabs(v[h][t])) + 1ULL;
-          kmax = key[h] > kmax ? key[h] : kmax;
-        }
-        {
-          // 64-bit wave max as two 32-bit DPP reductions (high word, then low)
-          const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
-          const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
-          kmax = ((unsigned long long)hi << 32) | lo;
-        }
-        int r = 64 * RPL;
-#pragma unroll
-        for (int h = RPL - 1; h >= 0; --h) {
-          const unsigned long long mk = __ballot(key[h] == kmax);
-          if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
-        }
-        double pv = 0.0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          colbuf[buf][lane + 64 * h] = v[h][t];
-          if ((r >> 6) == h) pv = readlane_f64(v[h][t], r & 63);
-        }
-        if (lane == 0) {
-          s_r[buf] = r;
-          s_pv[buf] = pv;
-        }
-      }
       __syncthreads();
       const int r = s_r[buf];
       const double pv = s_pv[buf];
@@ -151,37 +172,52 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
       // uniform: keep the pivot lane and row half in scalar registers
       const int rl = __builtin_amdgcn_readfirstlane(r & 63);
       const int rh = (RPL == 1) ? 0 : __builtin_amdgcn_readfirstlane(r >> 6);
-      // Broadcast the unscaled pivot row p (readlane), with p_c taken as 1.
-      // Row i != r becomes w_ij - (f_i q) p_j: the column-c slot, zeroed
-      // first, ends as -f_i q.  The pivot row uses f = 0 and is multiplied by
-      // q (its column-c slot set to 1 first, so it ends as q).
+      // the true pivot row p q (row r has scale 1: it has not pivoted yet);
+      // column c's slot takes q, so the other rows' slot ends as -f q
       double sp[CPW];
       if (RPL == 1 || rh == 0) {
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[0][j], rl);
+        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[0][j], rl) * q;
       } else {
 #pragma unroll
-        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[RPL - 1][j], rl);
+        for (int j = 0; j < CPW; ++j) sp[j] = readlane_f64(v[RPL - 1][j], rl) * q;
       }
-      sp[t] = owner ? 1.0 : sp[t];
+      sp[t] = owner ? q : sp[t];
+      double f[RPL];
 #pragma unroll
       for (int h = 0; h < RPL; ++h) {
         const int row = lane + 64 * h;
         const bool isr = (row == r);
-        const double fq = isr ? 0.0 : colbuf[buf][row] * q;
-        const double a = isr ? q : 1.0;
+        f[h] = isr ? 0.0 : colbuf[buf][row];
         v[h][t] = owner ? (isr ? 1.0 : 0.0) : v[h][t];
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) v[h][j] = fma(-fq, sp[j], v[h][j]) * a;
         used[h] = used[h] || isr;
         step_of[h] = isr ? c : step_of[h];
+        scale[h] = isr ? q : scale[h];
+      }
+      // column c + 1 first (slot s of wave (c + 1) / CPW), then its search
+      const int s = (t + 1) % CPW;  // a constant once the t loop is unrolled
+      const bool has_next = (c + 1 < NB);
+      const bool next_owner = (t + 1 < CPW) ? owner : (wave == cw + 1);
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) v[h][s] = fma(-f[h], sp[s], v[h][s]);
+      if (has_next && next_owner) {
+        double x[RPL];
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) x[h] = v[h][s];
+        leaf_search<RPL>(x, used, true, colbuf[buf ^ 1], &s_r[buf ^ 1], &s_pv[buf ^ 1], lane);
+      }
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+          if (j != s) v[h][j] = fma(-f[h], sp[j], v[h][j]);
       }
       if (tid == 0) piv_row[c] = r;
     }
   }
   if (singular) return;
   __syncthreads();
-  // A^-1[step_of(row)][piv_row[col]] = W[row][col]
+  // A^-1[step_of(row)][piv_row[col]] = scale(row) W[row][col]
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
     const int row = lane + 64 * h;
@@ -190,7 +226,7 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
       const int col = cbase + j;
-      if (col < b) dst[piv_row[col]] = v[h][j];
+      if (col < b) dst[piv_row[col]] = v[h][j] * scale[h];
     }
   }
 }
@@ -306,6 +342,10 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64
 template <int BM_, int BN_, int NWM_, int NWN_>
 struct TileCfg {
   static constexpr int BM = BM_, BN = BN_, NWM = NWM_, NWN = NWN_;
+  // waves per SIMD the register budget is sized for: two workgroups per CU
+  // for 128x128 tiles, one for the larger ones (whose accumulators need 128
+  // VGPRs per lane)
+  static constexpr int WPE = (BM_ * BN_ > 128 * 128) ? 2 : ((64 * NWM_ * NWN_ >= 512) ? 4 : 2);
   static constexpr int NT = 64 * NWM * NWN;
   static constexpr int BK = 16;
   static constexpr int PAD = 4;
@@ -502,7 +542,7 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
 
 template <int MODE, class C, bool A_KMAJOR, bool VEC>
 __global__ void __launch_bounds__(C::NT)
-__attribute__((amdgpu_waves_per_eu(C::NT >= 512 ? 4 : 2, C::NT >= 512 ? 4 : 2))) k_gemm_step(StepArgs g) {
+__attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g) {
   __shared__ double As[2][C::BK * C::LA];
   __shared__ double Bs[2][C::BK * C::LB];
   const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
@@ -682,6 +722,8 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
       return e ? atoi(e) : 1;
     }();
     if (cfg == 1) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
+    if (cfg == 2) return launch_step<MODE_SCHUR, 256, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
+    if (cfg == 3) return launch_step<MODE_SCHUR, 128, 256, true, 2, 4>(g, s, region, qo, qb, flops, slots);
     return launch_step<MODE_SCHUR, 128, 128, true, 2, 2>(g, s, region, qo, qb, flops, slots);
   }
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);

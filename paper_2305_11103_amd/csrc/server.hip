@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -34,7 +35,7 @@
 namespace {
 
 constexpr int kSmallMax = 128;     // orders batched into shared launches
-constexpr int kWorkers = 3;        // concurrent large requests
+constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 3)
 constexpr int kMaxRoundSmall = 65536;
 constexpr double kFp32Reach = 1e-6;  // rho the FP32 sweep can meet without refinement
 
@@ -101,7 +102,8 @@ struct binv_server {
   bool stop = false;
   std::thread sched;
   std::vector<std::thread> workers;
-  binv_ctx* wctx[kWorkers] = {nullptr};
+  int nworkers = 3;
+  binv_ctx* wctx[kMaxWorkers] = {nullptr};
   // Device blocks of finished requests, kept for reuse by size class so that
   // collecting a result never calls hipFree (which waits for the whole
   // device and would stall the other requests' work).
@@ -113,7 +115,7 @@ struct binv_server {
   // copies in and out of request state; every copy is waited for, so a
   // worker stream never reads a block before its input has landed
   hipStream_t cstream = nullptr;
-  binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo;
+  binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo, rwork, rtarget, rrho, rsteps;
   // statistics
   std::atomic<int64_t> completed{0};
 };
@@ -280,10 +282,16 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
       (e = s->rmats.ensure(sizeof(binv::SmallMat) * cnt)) != BINV_OK ||
       (e = s->rorder.ensure(sizeof(int32_t) * cnt)) != BINV_OK ||
       (e = s->rbounds.ensure(sizeof(int32_t) * bounds.size())) != BINV_OK ||
-      (e = s->rinfo.ensure(sizeof(int32_t) * cnt)) != BINV_OK) {
+      (e = s->rinfo.ensure(sizeof(int32_t) * cnt)) != BINV_OK ||
+      (e = s->rwork.ensure(sizeof(double) * 2 * std::max<int64_t>(off, 1))) != BINV_OK ||
+      (e = s->rtarget.ensure(sizeof(double) * cnt)) != BINV_OK ||
+      (e = s->rrho.ensure(sizeof(double) * cnt)) != BINV_OK ||
+      (e = s->rsteps.ensure(sizeof(int32_t) * cnt)) != BINV_OK) {
     err = "round buffers: out of device memory";
   }
-  std::vector<int32_t> hinfo(cnt, 0);
+  std::vector<int32_t> hinfo(cnt, 0), hsteps(cnt, 0);
+  std::vector<double> htarget(cnt), hrho(cnt, 0.0);
+  for (int64_t i = 0; i < cnt; ++i) htarget[i] = reqs[i]->target;
   if (e == BINV_OK) {
     hipError_t he = hipSuccess;
     double* A = (double*)s->rA.p;
@@ -298,10 +306,22 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
     for (int t = 0; t < 5 && he == hipSuccess; ++t)
       he = binv::launch_small_tier(t, A, X, (const binv::SmallMat*)s->rmats.p, (const int32_t*)s->rorder.p + first[t],
                                    count[t], (const int32_t*)s->rbounds.p, (int32_t*)s->rinfo.p, st);
+    // residual check of every matrix against its request's target, with up to
+    // three Newton-Schulz steps where it misses (a singular member's X is not
+    // used, so its refinement result does not matter)
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(s->rtarget.p, htarget.data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess)
+      he = binv::launch_small_refine(A, X, (const binv::SmallMat*)s->rmats.p, nullptr, cnt, (double*)s->rwork.p,
+                                     1e-10, (const double*)s->rtarget.p, 3, (double*)s->rrho.p,
+                                     (int32_t*)s->rsteps.p, st);
     for (int64_t i = 0; i < cnt && he == hipSuccess; ++i)
       he = hipMemcpyAsync(reqs[i]->dX, X + mats[i].off, sizeof(double) * mats[i].m * mats[i].m,
                           hipMemcpyDeviceToDevice, st);
     if (he == hipSuccess) he = hipMemcpyAsync(hinfo.data(), s->rinfo.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(hrho.data(), s->rrho.p, sizeof(double) * cnt, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(hsteps.data(), s->rsteps.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) {
       e = BINV_E_HIP;
@@ -310,8 +330,10 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
   }
   for (int64_t i = 0; i < cnt; ++i) {
     std::memset(&reqs[i]->info, 0, sizeof(binv_info));
-    reqs[i]->info.converged = 1;
-    reqs[i]->info.sampled = -1;  // Gauss-Jordan over the whole matrix; no residual formed
+    reqs[i]->info.rho = hrho[i];
+    reqs[i]->info.rho_steps[0] = hrho[i];
+    reqs[i]->info.refine_steps = hsteps[i];
+    reqs[i]->info.converged = hrho[i] <= reqs[i]->target;
     if (e != BINV_OK) finish(s, reqs[i], e, err);
     else if (hinfo[i] != 0)
       finish(s, reqs[i], BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo[i]));
@@ -408,7 +430,11 @@ binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_
     delete s;
     return sfail(BINV_E_HIP, "cannot use the device");
   }
-  for (int w = 0; w < kWorkers; ++w) {
+  if (const char* e = getenv("BINV_SERVER_WORKERS")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= kMaxWorkers) s->nworkers = v;
+  }
+  for (int w = 0; w < s->nworkers; ++w) {
     binv_status st = binv_create(&s->wctx[w], device);
     if (st != BINV_OK) {
       for (int v = 0; v < w; ++v) binv_destroy(s->wctx[v]);
@@ -419,7 +445,7 @@ binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_
     }
   }
   s->sched = std::thread(scheduler_main, s);
-  for (int w = 0; w < kWorkers; ++w) s->workers.emplace_back(worker_main, s, w);
+  for (int w = 0; w < s->nworkers; ++w) s->workers.emplace_back(worker_main, s, w);
   *out = s;
   return BINV_OK;
 }
@@ -553,8 +579,10 @@ binv_status binv_server_destroy(binv_server* s) {
     delete r;
   }
   for (auto& kv : s->pool) (void)hipFree(kv.second);
-  for (int w = 0; w < kWorkers; ++w) binv_destroy(s->wctx[w]);
-  for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo}) d->release();
+  for (int w = 0; w < s->nworkers; ++w) binv_destroy(s->wctx[w]);
+  for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork, &s->rtarget,
+                          &s->rrho, &s->rsteps})
+    d->release();
   if (s->rstream) (void)hipStreamDestroy(s->rstream);
   if (s->cstream) (void)hipStreamDestroy(s->cstream);
   delete s;

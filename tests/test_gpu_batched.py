@@ -165,3 +165,47 @@ def test_autotuned_shapes_are_bitwise_equal_to_default(gpu):
     assert torch.equal(X3, X0)
     for A_, Xi in zip(mats[::37], plan.unpack(X0.cpu().numpy())[::37]):
         check(A_, Xi, 1e-12)
+
+
+def test_device_residual_matches_oracle(gpu):
+    """binv_batch_residual: the device rho of every matrix agrees with the
+    oracle's compensated residual."""
+    import torch
+    from paper_2305_11103_amd import binv
+    sizes = [1, 3, 5, 17, 64, 65, 100, 128, 129, 200, 256]
+    mats = [wl.spd_gram(m, 900 + i) for i, m in enumerate(sizes)]
+    b = binv.Batch(sizes, ks=[min(m, 3) for m in sizes])
+    A = torch.from_numpy(b.pack(mats)).cuda()
+    X, info = b.invert(A, graph=False)
+    rho = b.residual(A, X).cpu().numpy()
+    Xh = b.unpack(X.cpu().numpy())
+    for Ai, Xi, r in zip(mats, Xh, rho):
+        ro = oracle.residual_stats(Ai, Xi)["rho"]
+        assert abs(r - ro) <= 0.25 * ro + 1e-16
+
+
+def test_small_refinement_in_server_meets_target(gpu):
+    """Ill-conditioned small requests: the server's residual check refines
+    them, and the device rho it reports agrees with the oracle."""
+    from paper_2305_11103_amd import binv
+    import time
+    srv = binv.Server(hbm_budget=1 << 30)
+    mats = [wl.general_haar(m, 950 + i, 1e6) for i, m in enumerate([20, 50, 90, 128])]
+    tickets = [srv.submit(A) for A in mats]
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets) and time.time() - t0 < 60:
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.002)
+    srv.close()
+    for A, t in zip(mats, tickets):
+        X, info, _ = out[t]
+        ro = oracle.residual_stats(A, X)["rho"]
+        r_o1 = oracle.residual_stats(A, oracle.gj_inverse(A))["rho"]
+        assert info["sampled"] == 0
+        assert abs(info["rho"] - ro) <= 0.25 * ro + 1e-16
+        assert ro <= max(1e-10, 2 * r_o1)

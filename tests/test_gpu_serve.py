@@ -71,7 +71,10 @@ def test_mix_matches_alone_bitwise_and_meets_target(gpu, strict, full_check):
         assert info["converged"]
         assert times["total_ms"] >= times["queue_ms"] >= 0
         assert np.array_equal(X, alone(A, n, prec, strict, full_check)), (n, prec)
-        assert info["sampled"] == (-1 if n <= 128 else (0 if full_check else info["sampled"]))
+        assert info["sampled"] == (0 if (n <= 128 or full_check) else info["sampled"])
+        if n <= 128:  # full residual measured on the device, no refinement needed here
+            assert info["refine_steps"] == 0
+            assert info["rho"] == pytest.approx(oracle.residual_stats(A, X)["rho"], rel=0.5, abs=1e-15)
         assert oracle.residual_stats(A, X)["rho"] <= 1e-10
     st = srv.stats()
     assert st["completed"] == len(reqs) and st["used"] == 0 and st["peak"] <= 8 << 30
