@@ -232,7 +232,10 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * in-flight limit allow.  Admitted requests of order <= 128 are grouped into
  * shared batched launches (one Gauss-Jordan pass each, pivoting over the
  * whole matrix); larger ones are inverted by the blockwise sweep on worker
- * threads with their own streams, so their work overlaps on the device.
+ * threads with their own streams, so their work overlaps on the device:
+ * orders >= 4096 one at a time on the first worker (with the lookahead
+ * schedule), orders 129..4095 on any worker (BINV_SERVER_WORKERS in the
+ * environment sets the worker count, default 3).
  * Every request of order > 128 ends with the FP64 residual check against its
  * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
@@ -272,6 +275,12 @@ binv_status binv_submit(binv_server* server, int64_t n, const double* A, int a_i
                         double target, uint64_t* ticket);
 binv_status binv_poll(binv_server* server, uint64_t ticket, double* X, int x_is_device, binv_info* info,
                       binv_request_times* times);
+/* Completion queue: the oldest finished, not yet collected ticket (in the
+ * order requests finished), waiting up to wait_us microseconds for one;
+ * BINV_E_BUSY if none.  The ticket stays valid for binv_poll, which collects
+ * it; a ticket collected without this call is skipped here. */
+binv_status binv_next_done(binv_server* server, int64_t wait_us, uint64_t* ticket);
+
 /* Device bytes currently held, the most ever held (never above the budget),
  * and requests finished so far.  Any pointer may be NULL. */
 binv_status binv_server_stats(binv_server* server, size_t* used_bytes, size_t* peak_bytes, int64_t* completed);

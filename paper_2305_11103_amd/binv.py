@@ -31,7 +31,8 @@ EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "bin
            "binv_invert_mixed",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
-           "binv_server_create", "binv_submit", "binv_poll", "binv_server_stats", "binv_server_destroy",
+           "binv_server_create", "binv_submit", "binv_poll", "binv_next_done", "binv_server_stats",
+           "binv_server_destroy",
            "binv_last_error", "binv_version")
 BINV_F_GRAPH = 4
 BINV_F_REFINE_FROM_FP64 = 8
@@ -108,6 +109,8 @@ def load_library():
     lib.binv_submit.restype = ctypes.c_int
     lib.binv_poll.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int, ctypes.POINTER(_Info), ctypes.POINTER(_Times)]
     lib.binv_poll.restype = ctypes.c_int
+    lib.binv_next_done.argtypes = [P, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.binv_next_done.restype = ctypes.c_int
     lib.binv_server_stats.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.binv_server_stats.restype = ctypes.c_int
@@ -462,6 +465,15 @@ class Server:
         info = {"rho": inf.rho, "refine_steps": inf.refine_steps, "fell_back": bool(inf.fell_back),
                 "converged": bool(inf.converged), "sampled": inf.sampled}
         return X, info, {"queue_ms": tm.queue_ms, "total_ms": tm.total_ms}
+
+    def next_done(self, wait_us=0):
+        """The oldest finished, uncollected ticket (waiting up to wait_us), or None."""
+        t = ctypes.c_uint64()
+        st = load_library().binv_next_done(self._h, int(wait_us), ctypes.byref(t))
+        if st == BINV_E_BUSY:
+            return None
+        _check(st)
+        return t.value
 
     def stats(self):
         u, p, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_int64()

@@ -117,6 +117,16 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
     }
   }
 
+  // columns at or beyond every matrix's order are identity padding of all
+  // the workgroup's matrices and are not eliminated (see the leaf kernel);
+  // the loop bound must be uniform over the workgroup because of the barriers
+  __shared__ int s_m[SUB];
+  if (wave == 0 && lane == 0) s_m[sub] = m;
+  __syncthreads();
+  int mmax = 0;
+#pragma unroll
+  for (int q = 0; q < SUB; ++q) mmax = s_m[q] > mmax ? s_m[q] : mmax;
+
   // current diagonal block [bs, be) of the column being eliminated (the
   // padding beyond m forms a last block of its own)
   int blk = 0;
@@ -130,10 +140,12 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
   }
   bool singular = false;
   for (int cw = 0; cw < NWV; ++cw) {
+    if (cw * CPW >= mmax) break;
     const bool owner = (wave == cw);
 #pragma unroll
     for (int t = 0; t < CPW; ++t) {
       const int c = cw * CPW + t;
+      if (c >= mmax) continue;
       const int buf = c & 1;
       __syncthreads();
       const int r = s_r[sub][buf];
@@ -176,7 +188,7 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
       const bool next_owner = (t + 1 < CPW) ? owner : (wave == cw + 1);
 #pragma unroll
       for (int h = 0; h < RPL; ++h) v[h][s] = fma(-f[h], sp[s], v[h][s]);
-      if (c + 1 < NB && next_owner) {
+      if (c + 1 < mmax && next_owner) {
         double x[RPL];
 #pragma unroll
         for (int h = 0; h < RPL; ++h) x[h] = v[h][s];

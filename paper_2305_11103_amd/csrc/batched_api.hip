@@ -52,7 +52,10 @@ binv_status upload(const std::vector<T>& h, void** d) {
 // One step of the swept tier: the jobs of all matrices that have a block s.
 struct SweptStep {
   int64_t first = 0, count = 0;  // range in the per-step job arrays
-  int bmax = 0;
+  int bmax = 0, mmax = 0;
+  // leaf jobs are ordered by block order, largest first, in four size
+  // classes (> 64, 33..64, 17..32, <= 16) launched with matching shapes
+  int64_t cls[4] = {0, 0, 0, 0};
   double row_flops = 0, schur_flops = 0;  // algorithmic flops of the step's GEMMs
   double leaf_flops = 0;                  // 2 b^3 per pivot block
 };
@@ -116,6 +119,7 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
   std::vector<binv::StepArgs> row, schur;
   double* ws = (double*)b->d_ws;
   for (size_t s = 0; s < b->steps.size(); ++s) {
+    const size_t leaf0 = leaf.size();
     for (size_t t = 0; t < b->swept.size(); ++t) {
       const int i = b->swept[t];
       const int mi = b->m[i];
@@ -145,6 +149,8 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
       sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs;
       schur.push_back(sa);
     }
+    std::stable_sort(leaf.begin() + leaf0, leaf.end(),
+                     [](const binv::LeafJob& x, const binv::LeafJob& y) { return x.b > y.b; });
   }
   binv_status st;
   if ((st = upload(leaf, &b->d_leaf)) != BINV_OK) return st;
@@ -174,17 +180,22 @@ binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hi
     {
       binv::PhaseTimer tm(c, lvl, BINV_PHASE_PIVOT, s);
       if (tm.on()) tm.flops = st.leaf_flops;
-      BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + st.first, st.count, st.bmax, s));
+      static const int kClassMax[4] = {128, 64, 32, 16};
+      int64_t at = st.first;
+      for (int q = 0; q < 4; ++q) {
+        BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + at, st.cls[q], kClassMax[q], s));
+        at += st.cls[q];
+      }
     }
     {
       binv::PhaseTimer tm(c, lvl, BINV_PHASE_ROW, s);
       if (tm.on()) tm.flops = st.row_flops;
-      BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, s));
+      BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, st.bmax, st.mmax, s));
     }
     {
       binv::PhaseTimer tm(c, lvl, BINV_PHASE_SCHUR, s);
       if (tm.on()) tm.flops = st.schur_flops;
-      BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, s));
+      BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, st.mmax, s));
     }
   }
   return BINV_OK;
@@ -317,6 +328,8 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
         const int bs = b->bounds_host[bi + s + 1] - b->bounds_host[bi + s];
         const double mi = b->m[i];
         st.bmax = std::max(st.bmax, bs);
+        st.mmax = std::max(st.mmax, b->m[i]);
+        st.cls[bs > 64 ? 0 : (bs > 32 ? 1 : (bs > 16 ? 2 : 3))]++;
         st.row_flops += 2.0 * bs * (double)bs * (mi - bs);
         st.leaf_flops += 2.0 * bs * (double)bs * bs;
         st.schur_flops += 2.0 * bs * (mi - bs) * mi;

@@ -54,6 +54,17 @@ namespace {
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
                   hipStream_t s, long long* info, int64_t row0, bool lookahead);
 
+// Order of the sub-blocks of the nested sweep that inverts a pivot block
+// larger than one leaf (BINV_SUB_BLOCK may set 32, 64 or 128).
+int sub_block() {
+  static const int v = [] {
+    const char* e = getenv("BINV_SUB_BLOCK");
+    const int x = e ? atoi(e) : binv::kSubBlock;
+    return (x == 32 || x == 64 || x == 128) ? x : binv::kSubBlock;
+  }();
+  return v;
+}
+
 binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw, int b, double* P, hipStream_t s,
                          long long* info, int64_t row0) {
   if (b <= binv::kLeafMax) {
@@ -64,7 +75,7 @@ binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw,
   // invert a copy in place by the same sweep with 64-wide sub-blocks, then use it as P
   HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
   std::vector<int32_t> sub;
-  for (int off = 0; off < b; off += binv::kSubBlock) sub.push_back(std::min(binv::kSubBlock, b - off));
+  for (int off = 0; off < b; off += sub_block()) sub.push_back(std::min(sub_block(), b - off));
   return sweep(c, level + 1, b, P, b, sub, s, info, row0, false);
 }
 
@@ -165,7 +176,7 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
     return BINV_OK;
   }
 
-  // Lookahead.  Step p: update block q = p+1's row/column band first (whole
+  // Lookahead.  Step p: update block q = p+1's diagonal block first (whole
   // device), then invert q's pivot block on the side stream (a few reserved
   // CUs) while the rest of step p's trailing update runs on the other CUs;
   // join, and form q's column and row panels.  The pivot chain is thus off the
@@ -178,8 +189,10 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
     const double* R = (const double*)L.r[cur].p;
     if (p + 1 < k) {
       {
+        // only block q's diagonal block must be current before its pivot
+        // inversion starts; its row and column bands join the rest
         PhaseTimer t(c, level, BINV_PHASE_BAND, s);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 1, off[p + 1], part[p + 1], s, t.fl(), 0));
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 3, off[p + 1], part[p + 1], s, t.fl(), 0));
       }
       HIP_TRY(hipEventRecord(c->ev_fork, s));
       HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
@@ -189,7 +202,7 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
       HIP_TRY(hipEventRecord(c->ev_join, c->side));
       {
         PhaseTimer t(c, level, BINV_PHASE_SCHUR, c->gemm);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 2, off[p + 1], part[p + 1], c->gemm,
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->gemm,
                                    t.fl(), 0));
       }
       HIP_TRY(hipEventRecord(c->ev_gemm, c->gemm));
@@ -307,7 +320,7 @@ binv_status parse_partition(int64_t n, const binv_opts* opts, std::vector<int32_
     for (int64_t off = 0; off < n; off += blk) part.push_back((int32_t)std::min<int64_t>(blk, n - off));
   }
   for (int32_t b : part)
-    if (b > binv::kLeafMax * binv::kSubBlock) return fail(BINV_E_INVALID, "diagonal block larger than 8192");
+    if (b > 8192) return fail(BINV_E_INVALID, "diagonal block larger than 8192");
   return BINV_OK;
 }
 
@@ -378,7 +391,7 @@ binv_status sweep_f32(binv_ctx* c, int64_t n, const double* A, int64_t lda, doub
         HIP_TRY(binv::launch_leaf_inverse(Pa, b, Pb, b, b, o, info, s));
       } else {
         std::vector<int32_t> sub;
-        for (int off = 0; off < b; off += binv::kSubBlock) sub.push_back(std::min(binv::kSubBlock, b - off));
+        for (int off = 0; off < b; off += sub_block()) sub.push_back(std::min(sub_block(), b - off));
         if ((st = sweep(c, 1, b, Pa, b, sub, s, info, o, false)) != BINV_OK) return st;
         Pinv = Pa;
       }

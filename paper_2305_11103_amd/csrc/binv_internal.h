@@ -74,8 +74,8 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
                         int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
 hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s);
-hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s);
-hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s);
+hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, int bmax, int mmax, hipStream_t s);
+hipError_t launch_schur_batched(const StepArgs* args, int64_t count, int mmax, hipStream_t s);
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);

@@ -27,6 +27,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "binv_internal.h"
@@ -152,12 +153,17 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
     leaf_search<RPL>(x, used, wave == 0, colbuf[0], &s_r[0], &s_pv[0], lane);
   }
 
+  // Columns b..NB-1 are identity padding: their rows hold zeros in the real
+  // columns (never updated, never chosen over a real row) and eliminating
+  // them would not touch the real block, so the loop stops at b (uniform).
   bool singular = false;
   for (int cw = 0; cw < NWV; ++cw) {
+    if (cw * CPW >= b) break;
     const bool owner = (wave == cw);
 #pragma unroll
     for (int t = 0; t < CPW; ++t) {
       const int c = cw * CPW + t;
+      if (c >= b) continue;
       const int buf = c & 1;
       __syncthreads();
       const int r = s_r[buf];
@@ -196,7 +202,7 @@ __device__ __forceinline__ void leaf_body(const double* __restrict__ A, int64_t 
       }
       // column c + 1 first (slot s of wave (c + 1) / CPW), then its search
       const int s = (t + 1) % CPW;  // a constant once the t loop is unrolled
-      const bool has_next = (c + 1 < NB);
+      const bool has_next = (c + 1 < b);
       const bool next_owner = (t + 1 < CPW) ? owner : (wave == cw + 1);
 #pragma unroll
       for (int h = 0; h < RPL; ++h) v[h][s] = fma(-f[h], sp[s], v[h][s]);
@@ -322,6 +328,13 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64
     tm = (mi < tr0) ? mi : mi + nr;
     return true;
   }
+  if (region == 3) {  // the diagonal tile block [tr0, tr1] x [tc0, tc1] only
+    const int64_t nc = tc1 - tc0 + 1;
+    if (t >= (tr1 - tr0 + 1) * nc) return false;
+    tm = tr0 + t / nc;
+    tn = tc0 + t % nc;
+    return true;
+  }
   if (t >= TM * TN) return false;
   const int64_t per_group = (int64_t)GM * TN;
   const int64_t group = t / per_group;
@@ -331,6 +344,7 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64
   tm = first + r % rows;
   tn = r / rows;
   if (region == 2 && ((tm >= tr0 && tm <= tr1) || (tn >= tc0 && tn <= tc1))) return false;
+  if (region == 4 && tm >= tr0 && tm <= tr1 && tn >= tc0 && tn <= tc1) return false;
   return true;
 }
 
@@ -560,23 +574,35 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g) {
 // column panel W[:, o:o+b] (from Win) row-major into g.A (ld g.lda = b), which
 // is then the m-major contraction operand.
 template <int MODE, class C, bool A_KMAJOR>
+// Workgroup (job, y): row panel: tile y of the job; Schur update: tile-row y
+// of the job.  A Schur tile-row reads and writes only its own rows of W, so
+// its workgroup first copies those rows' old column panel W[rows, o:o+b] into
+// the job's Ct (m-major, ld = b) and then updates the row's tiles, the
+// block-p columns included; no other workgroup touches those rows.
 __global__ void __launch_bounds__(C::NT) k_gemm_step_batched(const StepArgs* __restrict__ args) {
   __shared__ double As[2][C::BK * C::LA];
   __shared__ double Bs[2][C::BK * C::LB];
   const StepArgs g = args[blockIdx.x];
+  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
   if (MODE == MODE_SCHUR) {
+    const int64_t tm = blockIdx.y;
+    if (tm >= TM) return;
     double* Cp = const_cast<double*>(g.A);
-    const int64_t total = g.M * (int64_t)g.b;
+    const int64_t r0 = tm * C::BM;
+    const int64_t rows = (g.M - r0 < C::BM) ? g.M - r0 : C::BM;
+    const int64_t total = rows * (int64_t)g.b;
     for (int64_t e = threadIdx.x; e < total; e += C::NT) {
-      const int64_t i = e / g.b;
-      const int t = (int)(e - i * g.b);
+      const int64_t i = r0 + e / g.b;
+      const int t = (int)(e % g.b);
       Cp[i * g.lda + t] = g.Win[i * g.ldwin + g.o + t];
     }
     __syncthreads();
-  }
-  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
-  for (int64_t tm = 0; tm < TM; ++tm)
     for (int64_t tn = 0; tn < TN; ++tn) gemm_tile<MODE, C, A_KMAJOR, false>(g, tm, tn, As, Bs);
+  } else {
+    const int64_t t = blockIdx.y;
+    if (t >= TM * TN) return;
+    gemm_tile<MODE, C, A_KMAJOR, false>(g, t / TN, t % TN, As, Bs);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -644,8 +670,11 @@ static double step_flops(const StepArgs& g, int mode) {
       if (z > a) rows -= z - a;
     }
     for (int64_t tn = 0; tn < TN; ++tn) {
+      const bool indiag = tm >= g.tr0 && tm <= g.tr1 && tn >= g.tc0 && tn <= g.tc1;
       if (g.region == 1 && !inband(tm, tn)) continue;
       if (g.region == 2 && inband(tm, tn)) continue;
+      if (g.region == 3 && !indiag) continue;
+      if (g.region == 4 && indiag) continue;
       const int64_t c0 = tn * BN, c1 = (c0 + BN < g.N) ? c0 + BN : g.N;
       int64_t cols = c1 - c0;
       if (mode == MODE_ROW) {
@@ -674,6 +703,7 @@ static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo,
     g.tc0 = qo / BN;
     g.tc1 = (qo + qb - 1) / BN;
     if (region == 1) T = (g.tr1 - g.tr0 + 1) * TN + (TM - (g.tr1 - g.tr0 + 1)) * (g.tc1 - g.tc0 + 1);
+    if (region == 3) T = (g.tr1 - g.tr0 + 1) * (g.tc1 - g.tc0 + 1);
   }
   if (flops) *flops = step_flops<BM, BN>(g, MODE);
   g.ntiles = T;
@@ -704,7 +734,9 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 
 // Schur trailing update in place on W using the saved column panel Ct (b x n,
 // k-major) and the row panel R (b x n).  region 0: all tiles; 1: only the
-// tile band covering rows/columns [qo, qo+qb) of the next block; 2: the rest.
+// tile band covering rows/columns [qo, qo+qb) of the next block; 2: the rest;
+// 3: only the tiles of the next block's diagonal block (rows and columns
+// [qo, qo+qb)); 4: every tile but those.
 int schur_tile(int64_t n) { return n >= 2048 ? 128 : 64; }
 
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
@@ -716,6 +748,15 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   g.Win = W; g.ldwin = ldw;
   g.R = R; g.ldr = ldr;
   g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
+  if (region == 3) {
+    // the next block's diagonal tiles of the trailing-update grid, updated
+    // with 64 x 64 tiles (more workgroups for this short launch) over exactly
+    // the element range those grid tiles cover
+    const int64_t tile = schur_tile(n);
+    const int64_t a0 = qo / tile * tile;
+    const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
+    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0);
+  }
   if (schur_tile(n) == 128) {
     static const int cfg = [] {
       const char* e = getenv("BINV_SCHUR_CFG");
@@ -762,7 +803,9 @@ hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int6
 hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const dim3 g((unsigned)count);
-  if (bmax <= 32)
+  if (bmax <= 16)
+    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 4, 4>), g, dim3(256), 0, s, jobs);
+  else if (bmax <= 32)
     hipLaunchKernelGGL((k_leaf_inverse_batched<1, 8, 4>), g, dim3(256), 0, s, jobs);
   else if (bmax <= 64)
     hipLaunchKernelGGL((k_leaf_inverse_batched<1, 16, 4>), g, dim3(256), 0, s, jobs);
@@ -771,17 +814,20 @@ hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hip
   return hipGetLastError();
 }
 
-hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, hipStream_t s) {
+// bmax, mmax: the largest block and matrix order among the jobs (they size
+// the second grid dimension; surplus workgroups return at once).
+hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, int bmax, int mmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_step_batched<MODE_ROW, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count), dim3(256), 0,
-                     s, args);
+  const unsigned tiles = (unsigned)(((bmax + 63) / 64) * ((mmax + 63) / 64));
+  hipLaunchKernelGGL((k_gemm_step_batched<MODE_ROW, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count, tiles),
+                     dim3(256), 0, s, args);
   return hipGetLastError();
 }
 
-hipError_t launch_schur_batched(const StepArgs* args, int64_t count, hipStream_t s) {
+hipError_t launch_schur_batched(const StepArgs* args, int64_t count, int mmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count), dim3(256),
-                     0, s, args);
+  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, false>),
+                     dim3((unsigned)count, (unsigned)((mmax + 63) / 64)), dim3(256), 0, s, args);
   return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ namespace {
 constexpr int kSmallMax = 128;     // orders batched into shared launches
 constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 3)
 constexpr int kMaxRoundSmall = 65536;
+constexpr int64_t kBigN = 4096;    // orders served one at a time on worker 0
 constexpr double kFp32Reach = 1e-6;  // rho the FP32 sweep can meet without refinement
 
 double now_s() {
@@ -91,13 +92,15 @@ struct binv_server {
   std::condition_variable cv;      // wakes the scheduler
   std::condition_variable wcv;     // wakes the workers
   std::deque<Request*> queue;      // submitted, not admitted
-  std::deque<Request*> large_ready;
+  std::deque<Request*> big_ready;   // order >= kBigN: worker 0 only, one at a time
+  std::deque<Request*> mid_ready;   // kSmallMax < order < kBigN: any worker
   std::vector<Request*> small_ready;
   std::unordered_map<uint64_t, Request*> all;
+  std::deque<uint64_t> done_q;     // finished tickets in completion order
+  std::condition_variable dcv;     // wakes binv_next_done
   size_t used = 0;
   size_t peak = 0;
   int inflight = 0;
-  int large_running = 0;           // large requests on workers right now
   uint64_t next_id = 1;
   bool stop = false;
   std::thread sched;
@@ -130,7 +133,9 @@ void finish(binv_server* s, Request* r, binv_status st, const std::string& err) 
   r->t_done = now_s();
   s->inflight--;
   s->completed++;
+  s->done_q.push_back(r->id);
   s->cv.notify_all();
+  s->dcv.notify_all();
 }
 
 hipError_t copy_sync(binv_server* s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
@@ -207,6 +212,21 @@ void request_release(binv_server* s, Request* r) {
   r->dA = r->dX = nullptr;
 }
 
+// Queue an admitted request for its lane (mu held).  Large orders run one at
+// a time on worker 0, with the lookahead schedule: one sweep of that size
+// already keeps the device busy, and two of them side by side were measured
+// slower than one after the other.  Mid orders are latency-bound sweeps that
+// the other workers overlap with it and with each other.
+void route_locked(binv_server* s, Request* r) {
+  if (r->n <= kSmallMax) {
+    s->small_ready.push_back(r);
+    return;
+  }
+  if (r->n >= kBigN) s->big_ready.push_back(r);
+  else s->mid_ready.push_back(r);
+  s->wcv.notify_all();
+}
+
 // Admit queued requests in order while memory and slots allow (mu held).
 void admit_locked(binv_server* s) {
   while (!s->queue.empty() && s->inflight < s->max_inflight) {
@@ -216,11 +236,7 @@ void admit_locked(binv_server* s) {
       s->inflight++;
       r->state = Q_ADMITTED;
       r->t_admit = now_s();
-      if (r->n <= kSmallMax) s->small_ready.push_back(r);
-      else {
-        s->large_ready.push_back(r);
-        s->wcv.notify_one();
-      }
+      route_locked(s, r);
       continue;
     }
     if (s->used + r->bytes > s->budget) break;  // wait until results are collected
@@ -238,11 +254,7 @@ void admit_locked(binv_server* s) {
     s->inflight++;
     r->state = Q_ADMITTED;
     r->t_admit = now_s();
-    if (r->n <= kSmallMax) s->small_ready.push_back(r);
-    else {
-      s->large_ready.push_back(r);
-      s->wcv.notify_one();
-    }
+    route_locked(s, r);
   }
 }
 
@@ -369,24 +381,25 @@ void worker_main(binv_server* s, int w) {
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   for (;;) {
     Request* r = nullptr;
-    bool alone = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->wcv.wait(lk, [&] { return s->stop || !s->large_ready.empty(); });
-      if (s->stop && s->large_ready.empty()) break;
-      r = s->large_ready.front();
-      s->large_ready.pop_front();
+      // worker 0 takes large orders first; every worker takes mid orders
+      auto ready = [&] { return !s->mid_ready.empty() || (w == 0 && !s->big_ready.empty()); };
+      s->wcv.wait(lk, [&] { return s->stop || ready(); });
+      if (s->stop && !ready()) break;
+      std::deque<Request*>& q = (w == 0 && !s->big_ready.empty()) ? s->big_ready : s->mid_ready;
+      r = q.front();
+      q.pop_front();
       r->state = Q_RUNNING;
-      alone = s->large_running++ == 0;
     }
     binv_status e;
     std::memset(&r->info, 0, sizeof(binv_info));
     binv_opts o;
     std::memset(&o, 0, sizeof(o));
     o.block = r->n >= 2048 ? 512 : (r->n >= 512 ? 256 : 128);
-    // lookahead (a CU-masked side stream for the pivot chain) only pays when
-    // no other large request is there to fill the device meanwhile
-    o.flags = BINV_F_SYNC | ((r->n < 4096 || !alone) ? BINV_F_NO_LOOKAHEAD : 0u);
+    // lookahead (a CU-masked side stream for the pivot chain) for the large
+    // lane only; mid-size sweeps overlap each other instead
+    o.flags = BINV_F_SYNC | (r->n < kBigN ? BINV_F_NO_LOOKAHEAD : 0u);
     // Every request ends with the FP64 residual check against its target
     // (sampled rows unless BINV_SERVER_FULL_CHECK) and is refined only if the
     // check fails.  An FP64 request starts from the FP64 sweep.  A mixed
@@ -400,10 +413,6 @@ void worker_main(binv_server* s, int w) {
     if (!(s->flags & BINV_SERVER_FULL_CHECK)) o.flags |= BINV_F_SAMPLED_CHECK;
     e = binv_invert_mixed(s->wctx[w], r->n, r->dA, r->n, r->dX, r->n, &o, r->target, -1, st, &r->info);
     r->fp32_start = fp32_start;
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      s->large_running--;
-    }
     finish(s, r, e, e == BINV_OK ? "" : binv_last_error());
   }
   if (st) (void)hipStreamDestroy(st);
@@ -553,6 +562,31 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
   return st;
 }
 
+binv_status binv_next_done(binv_server* s, int64_t wait_us, uint64_t* ticket) {
+  if (!s || !ticket) return sfail(BINV_E_INVALID, "NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto pop = [&]() -> bool {
+    while (!s->done_q.empty()) {
+      const uint64_t t = s->done_q.front();
+      s->done_q.pop_front();
+      if (s->all.count(t)) {  // not collected yet
+        *ticket = t;
+        return true;
+      }
+    }
+    return false;
+  };
+  if (pop()) return BINV_OK;
+  if (wait_us > 0) {
+    const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(wait_us);
+    while (!s->stop && std::chrono::steady_clock::now() < until) {
+      s->dcv.wait_until(lk, until);
+      if (pop()) return BINV_OK;
+    }
+  }
+  return BINV_E_BUSY;
+}
+
 binv_status binv_server_stats(binv_server* s, size_t* used, size_t* peak, int64_t* completed) {
   if (!s) return sfail(BINV_E_INVALID, "server is NULL");
   std::lock_guard<std::mutex> g(s->mu);
@@ -569,6 +603,7 @@ binv_status binv_server_destroy(binv_server* s) {
     s->stop = true;
     s->cv.notify_all();
     s->wcv.notify_all();
+    s->dcv.notify_all();
   }
   if (s->sched.joinable()) s->sched.join();
   for (auto& t : s->workers)

@@ -239,18 +239,40 @@ def request_stream(count: int, seed: int, lo: int = 5, hi: int = 8192):
 def householder_conditioned_device(n: int, seed: int, cond: float, device, reflectors: int = 4):
     """U diag(pi(s)) V^T with U and V each a product of `reflectors` random
     Householder reflectors and pi a random permutation of geometric singular
-    values from 1 to 1/cond (so the condition number is exactly cond), formed
-    on the device in O(n^2) work."""
+    values from 1 to 1/cond (so the condition number is exactly cond).
+
+    Draws: the permutation, then the left reflector vectors u_1..u_r (applied
+    in that order, U = H(u_r)...H(u_1)), then the right ones v_1..v_r (V^T =
+    H(v_1)...H(v_r)), all from one PCG64 stream.  Formed on the device in
+    O(n^2) work as diag(pi(s)) plus a rank-(3r) product: each reflector
+    product is written I - W Y^T (compact WY: appending H(u) = I - 2 u u^T to
+    I - W Y^T appends the column 2 (u - W Y^T u) to W and u to Y), and
+    (I - Wu Yu^T) D (I - Wv Yv^T) = D - Wu (Yu^T D) - (D Wv) Yv^T
+    + Wu (Yu^T D Wv) Yv^T is one GEMM of inner dimension 3r."""
     import torch
     g = np.random.Generator(np.random.PCG64(seed & 0xFFFFFFFFFFFFFFFF))
-    s = geometric_singular_values(n, cond)[g.permutation(n)]
-    A = torch.diag(torch.from_numpy(s).to(device))
-    for side in (0, 1):
-        for _ in range(reflectors):
-            v = torch.from_numpy(g.standard_normal(n)).to(device)
-            v = v / torch.linalg.vector_norm(v)
-            if side == 0:
-                A -= 2.0 * torch.outer(v, v @ A)
-            else:
-                A -= 2.0 * torch.outer(A @ v, v)
+    s = torch.from_numpy(geometric_singular_values(n, cond)[g.permutation(n)]).to(device)
+    vecs = []
+    for _ in range(2 * reflectors):
+        v = torch.from_numpy(g.standard_normal(n)).to(device)
+        vecs.append(v / torch.linalg.vector_norm(v))
+
+    def wy(seq):
+        W = torch.zeros((n, 0), dtype=torch.float64, device=device)
+        Y = torch.zeros((n, 0), dtype=torch.float64, device=device)
+        for u in seq:
+            w = 2.0 * (u - W @ (Y.T @ u))
+            W = torch.cat([W, w[:, None]], dim=1)
+            Y = torch.cat([Y, u[:, None]], dim=1)
+        return W, Y
+
+    Wu, Yu = wy(reversed(vecs[:reflectors]))   # U = H(u_r) ... H(u_1)
+    Wv, Yv = wy(vecs[reflectors:])             # V^T = H(v_1) ... H(v_r)
+    P = Yu.T * s[None, :]                      # Yu^T D
+    Q = Wv * s[:, None]                        # D Wv
+    M = P @ Wv                                 # Yu^T D Wv
+    L = torch.cat([-Wu, -Q, Wu @ M], dim=1)
+    R = torch.cat([P, Yv.T, Yv.T], dim=0)
+    A = L @ R
+    A.diagonal().add_(s)
     return A

@@ -115,3 +115,26 @@ def test_budget_and_ticket_errors(gpu):
     with pytest.raises(binv.BinvError):
         srv.poll(12345)
     srv.close()
+
+
+def test_completion_queue_returns_every_ticket_once(gpu):
+    """binv_next_done hands out each finished ticket exactly once, in
+    completion order, and skips tickets collected directly."""
+    from paper_2305_11103_amd import binv
+    srv = binv.Server(hbm_budget=2 << 30)
+    mats = [wl.spd_gram(m, 60 + i) for i, m in enumerate([5, 40, 130, 300, 8, 600])]
+    tickets = [srv.submit(A) for A in mats]
+    first = wait_all(srv, tickets[:1])  # collected directly: never handed out
+    seen = []
+    t0 = time.time()
+    while len(seen) < len(tickets) - 1 and time.time() - t0 < 60:
+        t = srv.next_done(wait_us=20000)
+        if t is not None:
+            seen.append(t)
+            X, info, _ = srv.poll(t)
+            A = mats[tickets.index(t)]
+            assert oracle.residual_stats(A, X)["rho"] <= 1e-12
+    assert sorted(seen) == sorted(tickets[1:])
+    assert srv.next_done() is None
+    assert isinstance(first[tickets[0]], tuple)
+    srv.close()

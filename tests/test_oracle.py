@@ -327,3 +327,4 @@ def test_ns_converges_quadratically():
         X = oracle.ns_step(A, X)
         r.append(oracle.residual_stats(A, X)["rho"])
     assert r[1] < 10 * r[0] ** 2 + 1e-14 and r[2] < 1e-13
+
