@@ -590,10 +590,11 @@ __global__ void __launch_bounds__(C::NT) k_gemm_step_batched(const StepArgs* __r
     double* Cp = const_cast<double*>(g.A);
     const int64_t r0 = tm * C::BM;
     const int64_t rows = (g.M - r0 < C::BM) ? g.M - r0 : C::BM;
-    const int64_t total = rows * (int64_t)g.b;
-    for (int64_t e = threadIdx.x; e < total; e += C::NT) {
-      const int64_t i = r0 + e / g.b;
-      const int t = (int)(e % g.b);
+    const int total = (int)rows * g.b;  // <= 64 x 128
+    for (int e = threadIdx.x; e < total; e += C::NT) {
+      const int q = e / g.b;
+      const int t = e - q * g.b;
+      const int64_t i = r0 + q;
       Cp[i * g.lda + t] = g.Win[i * g.ldwin + g.o + t];
     }
     __syncthreads();

@@ -209,3 +209,30 @@ def test_small_refinement_in_server_meets_target(gpu):
         assert info["sampled"] == 0
         assert abs(info["rho"] - ro) <= 0.25 * ro + 1e-16
         assert ro <= max(1e-10, 2 * r_o1)
+
+
+def test_full_batch_configuration(gpu):
+    """The benchmark's batch (100000 x 5^2 + 20000 x U{8..256}^2 SPD, k in
+    {2,3,4} near-equal blocks), autotuned and replayed as a graph: every
+    matrix's device rho <= 1e-12 and 200 sampled matrices elementwise against
+    the oracle."""
+    import torch
+    from paper_2305_11103_amd import binv
+    sizes, parts = wl.batch_spec(wl.stream_seed(4, 0))
+    mats = wl.spd_gram_batch(sizes, wl.stream_seed(4, 1))
+    b = binv.Batch(sizes, parts=parts)
+    A = torch.from_numpy(b.pack(mats)).cuda()
+    X = torch.empty_like(A)
+    info = torch.empty(b.count, dtype=torch.int32, device="cuda")
+    b.tune(A, X, info=info, reps=1)
+    X2, info2 = b.invert(A, info=info, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(X2, X)  # tuned shapes: same bits as the tuner's own pass
+    assert int(info2.abs().max().item()) == 0
+    rho = b.residual(A, X2)
+    assert float(rho.max().item()) <= 1e-12
+    Xh = b.unpack(X2.cpu().numpy())
+    rng = np.random.default_rng(3)
+    pick = np.unique(np.concatenate([rng.choice(len(sizes), 180, replace=False), np.argsort(sizes)[-20:]]))
+    for i in pick:
+        check(mats[i], Xh[i], 1e-12 if sizes[i] > 1 else 1e-15)

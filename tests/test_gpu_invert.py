@@ -178,3 +178,25 @@ def test_timing_reports_flops(gpu):
     assert t["schur"][2] + t["band"][2] == pytest.approx(k * 2.0 * blk * (n - blk) * n)
     assert t["row"][2] == pytest.approx(k * 2.0 * blk * blk * (n - blk))
     assert t["schur"][1] == k and t["band"][1] == k - 1
+
+
+def test_full_size_bench_configuration(gpu):
+    """The benchmark's own configuration (n = 8192, 16 x 16 grid of 512-blocks,
+    SPD Q diag(s) Q^T with cond 1e4, lookahead schedule), checked through
+    properties that hold at any size: the oracle's compensated residual on 48
+    sampled rows, and the symmetry of the inverse of a symmetric matrix on the
+    sampled rows and columns."""
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 8192
+    A = wl.spd_haar_device(n, wl.stream_seed(2, 0), 1e4, "cuda").contiguous()
+    X = binv.invert(A, block=512, lookahead=True)
+    torch.cuda.synchronize()
+    An, Xn = A.cpu().numpy(), X.cpu().numpy()
+    rows = np.sort(np.random.default_rng(21).choice(n, 48, replace=False))
+    st = oracle.residual_stats(An, Xn, rows)
+    assert st["rho"] <= 1e-10, st
+    assert np.isfinite(Xn).all()
+    # the inverse of a symmetric matrix is symmetric: rounding-level asymmetry only
+    asym = np.max(np.abs(Xn[rows][:, rows] - Xn[rows][:, rows].T)) / np.max(np.abs(Xn))
+    assert asym <= 1e-9

@@ -106,3 +106,20 @@ def test_sampled_check_refines_when_the_sweep_misses(gpu):
     torch.cuda.synchronize()
     assert info["refine_steps"] >= 1 and info["converged"]
     assert oracle.residual_stats(A, X.cpu().numpy())["rho"] <= 1e-10
+
+
+def test_full_size_mixed_configuration(gpu):
+    """The mixed-precision workload's size (n = 16384, 32 x 32 grid of
+    512-blocks, U diag(s) V^T with cond 1e2): the result meets the target on
+    the oracle's compensated residual over sampled rows."""
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 16384
+    A = wl.general_haar_device(n, wl.stream_seed(3, 0), 1e2, "cuda").contiguous()
+    X, info = binv.invert_mixed(A, block=512)
+    torch.cuda.synchronize()
+    assert info["converged"]
+    rows = np.sort(np.random.default_rng(8).choice(n, 12, replace=False))
+    An = A.cpu().numpy()
+    Xn = X.cpu().numpy()
+    assert oracle.residual_stats(An, Xn, rows)["rho"] <= 1e-10
