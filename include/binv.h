@@ -239,7 +239,9 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * Every request of order > 128 ends with the FP64 residual check against its
  * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
- * fails.  BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
+ * fails; the check asks for half the target (it carries rounding and
+ * sampling error of its own), info->converged reports rho <= target.
+ * BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
  * the FP32 sweep under the policy of BINV_SERVER_STRICT_PRECISION below.
  * Requests of order <= 128 are inverted in FP64 (Gauss-Jordan with pivoting
  * over the whole matrix, shared launches), then checked on their full
@@ -250,7 +252,8 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * *times (either may be NULL), releases the request's device memory and
  * forgets the ticket.  A finished request keeps its memory until it is
  * polled; the server then keeps the block for reuse by later requests (at
- * most the budget's worth of cached blocks, freed by binv_server_destroy).  Errors: BINV_E_NOMEM from binv_submit when the request alone
+ * most a quarter of the budget in cached blocks, freed by
+ * binv_server_destroy).  Errors: BINV_E_NOMEM from binv_submit when the request alone
  * exceeds the budget; BINV_E_SINGULAR (and the other codes) from binv_poll
  * for a request that failed.
  * --------------------------------------------------------------------------- */

@@ -3,10 +3,10 @@
 // A plan fixes the orders and diagonal-block partitions of a batch of small
 // matrices packed back to back.  Matrices of order <= 128 go to one of five
 // register-resident tiers (k_small_inverse: one pass, pivoting restricted to
-// each diagonal block); orders 129..256 are swept block by block with batched
-// step kernels (one workgroup per matrix: pivot leaf, column-panel save, row
-// panel, Schur update with the column panel saved in-kernel), the same Eq. (a)
-// step as the single-matrix path.  All
+// each diagonal block); orders 129..256 are swept block by block, one launch
+// per step and shape class with one workgroup per matrix doing the whole step
+// (k_swept_step: pivot leaf, row panel, column-panel copy, Schur update), the
+// same Eq. (a) step as the single-matrix path.  All
 // job tables live on the device, so a run is a fixed sequence of launches that
 // is captured once into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
@@ -53,9 +53,9 @@ binv_status upload(const std::vector<T>& h, void** d) {
 struct SweptStep {
   int64_t first = 0, count = 0;  // range in the per-step job arrays
   int bmax = 0, mmax = 0;
-  // leaf jobs are ordered by block order, largest first, in four size
-  // classes (> 64, 33..64, 17..32, <= 16) launched with matching shapes
-  int64_t cls[4] = {0, 0, 0, 0};
+  // jobs are ordered by pivot-block order, largest first, in two shape
+  // classes: cls[0] with blocks > 64, cls[1] with blocks <= 64
+  int64_t cls[2] = {0, 0};
   double row_flops = 0, schur_flops = 0;  // algorithmic flops of the step's GEMMs
   double leaf_flops = 0;                  // 2 b^3 per pivot block
 };
@@ -85,9 +85,7 @@ struct binv_batch {
   const void* bound_A = nullptr;
   void* bound_X = nullptr;
   void* bound_info = nullptr;
-  void* d_leaf = nullptr;
-  void* d_row = nullptr;
-  void* d_schur = nullptr;
+  void* d_jobs = nullptr;  // SweptJob per (step, swept matrix)
   // graph of the whole run for the current binding
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -99,10 +97,8 @@ struct binv_batch {
 namespace {
 
 void free_bindings(binv_batch* b) {
-  for (void** p : {&b->d_leaf, &b->d_row, &b->d_schur}) {
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-  }
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  b->d_jobs = nullptr;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
@@ -112,14 +108,15 @@ void free_bindings(binv_batch* b) {
   b->bound_info = nullptr;
 }
 
-// Build the per-step job tables of the swept tier for buffers (A, X, info).
+// Build the per-step job table of the swept tier for buffers (A, X, info):
+// one job per (step, matrix), each step's jobs ordered by pivot-block order,
+// largest first, so that the two shape classes (> 64, <= 64) are contiguous.
 binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
   free_bindings(b);
-  std::vector<binv::LeafJob> leaf;
-  std::vector<binv::StepArgs> row, schur;
+  std::vector<binv::SweptJob> jobs;
   double* ws = (double*)b->d_ws;
   for (size_t s = 0; s < b->steps.size(); ++s) {
-    const size_t leaf0 = leaf.size();
+    const size_t first = jobs.size();
     for (size_t t = 0; t < b->swept.size(); ++t) {
       const int i = b->swept[t];
       const int mi = b->m[i];
@@ -133,29 +130,24 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
       double* P = ws + b->ws_off[t];
       double* Ct = P + kBlockMax * kBlockMax;
       double* R = Ct + (int64_t)kBlockMax * mi;
-      binv::LeafJob lj;
-      lj.A = Win + (int64_t)o * mi + o; lj.lda = mi; lj.P = P; lj.ldp = bs; lj.b = bs; lj.row0 = o;
-      lj.info = info + i;
-      leaf.push_back(lj);
-      binv::StepArgs ra;
-      std::memset(&ra, 0, sizeof(ra));
+      binv::SweptJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.leaf.A = Win + (int64_t)o * mi + o; j.leaf.lda = mi; j.leaf.P = P; j.leaf.ldp = bs; j.leaf.b = bs;
+      j.leaf.row0 = o; j.leaf.info = info + i;
+      binv::StepArgs& ra = j.row;
       ra.A = P; ra.lda = bs; ra.B = Win + (int64_t)o * mi; ra.ldb = mi; ra.W = R; ra.ldw = mi;
-      ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = mi; ra.K = bs; ra.o = o; ra.b = bs;
-      row.push_back(ra);
-      binv::StepArgs sa;
-      std::memset(&sa, 0, sizeof(sa));
-      // the Schur kernel copies the old column panel into Ct (row-major, ld = b) first
+      ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = mi; ra.K = bs; ra.o = o; ra.b = bs; ra.dstride = 1;
+      binv::StepArgs& sa = j.schur;
+      // the old column panel goes to Ct (m-major, ld = b) before the update
       sa.A = Ct; sa.lda = bs; sa.B = R; sa.ldb = mi; sa.W = Wout; sa.ldw = mi; sa.Win = Win; sa.ldwin = mi;
-      sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs;
-      schur.push_back(sa);
+      sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs; sa.dstride = 1;
+      jobs.push_back(j);
     }
-    std::stable_sort(leaf.begin() + leaf0, leaf.end(),
-                     [](const binv::LeafJob& x, const binv::LeafJob& y) { return x.b > y.b; });
+    std::stable_sort(jobs.begin() + first, jobs.end(),
+                     [](const binv::SweptJob& x, const binv::SweptJob& y) { return x.leaf.b > y.leaf.b; });
   }
   binv_status st;
-  if ((st = upload(leaf, &b->d_leaf)) != BINV_OK) return st;
-  if ((st = upload(row, &b->d_row)) != BINV_OK) return st;
-  if ((st = upload(schur, &b->d_schur)) != BINV_OK) return st;
+  if ((st = upload(jobs, &b->d_jobs)) != BINV_OK) return st;
   b->bound_A = A;
   b->bound_X = X;
   b->bound_info = info;
@@ -177,26 +169,12 @@ binv_status enqueue(binv_batch* b, const double* A, double* X, int32_t* info, hi
                                  (const int32_t*)b->d_bounds, info, s));
   }
   for (const SweptStep& st : b->steps) {
-    {
-      binv::PhaseTimer tm(c, lvl, BINV_PHASE_PIVOT, s);
-      if (tm.on()) tm.flops = st.leaf_flops;
-      static const int kClassMax[4] = {128, 64, 32, 16};
-      int64_t at = st.first;
-      for (int q = 0; q < 4; ++q) {
-        BHIP(binv::launch_leaf_batched((const binv::LeafJob*)b->d_leaf + at, st.cls[q], kClassMax[q], s));
-        at += st.cls[q];
-      }
-    }
-    {
-      binv::PhaseTimer tm(c, lvl, BINV_PHASE_ROW, s);
-      if (tm.on()) tm.flops = st.row_flops;
-      BHIP(binv::launch_row_panel_batched((const binv::StepArgs*)b->d_row + st.first, st.count, st.bmax, st.mmax, s));
-    }
-    {
-      binv::PhaseTimer tm(c, lvl, BINV_PHASE_SCHUR, s);
-      if (tm.on()) tm.flops = st.schur_flops;
-      BHIP(binv::launch_schur_batched((const binv::StepArgs*)b->d_schur + st.first, st.count, st.mmax, s));
-    }
+    // one workgroup per matrix does the whole step (leaf, row panel, Schur)
+    binv::PhaseTimer tm(c, lvl, BINV_PHASE_SCHUR, s);
+    if (tm.on()) tm.flops = st.leaf_flops + st.row_flops + st.schur_flops;
+    const binv::SweptJob* jobs = (const binv::SweptJob*)b->d_jobs + st.first;
+    BHIP(binv::launch_swept_step(jobs, st.cls[0], 128, s));
+    BHIP(binv::launch_swept_step(jobs + st.cls[0], st.count - st.cls[0], 64, s));
   }
   return BINV_OK;
 }
@@ -329,7 +307,7 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
         const double mi = b->m[i];
         st.bmax = std::max(st.bmax, bs);
         st.mmax = std::max(st.mmax, b->m[i]);
-        st.cls[bs > 64 ? 0 : (bs > 32 ? 1 : (bs > 16 ? 2 : 3))]++;
+        st.cls[bs > 64 ? 0 : 1]++;
         st.row_flops += 2.0 * bs * (double)bs * (mi - bs);
         st.leaf_flops += 2.0 * bs * (double)bs * bs;
         st.schur_flops += 2.0 * bs * (mi - bs) * mi;

@@ -59,6 +59,15 @@ struct LeafJob {
   int* info;  // the matrix's info word
 };
 
+// One step of one matrix of the batched sweep, done by one workgroup: the
+// pivot block's inverse (leaf), the row panel, then the Schur update with the
+// old column panel copied first.
+struct SweptJob {
+  LeafJob leaf;
+  StepArgs row;
+  StepArgs schur;
+};
+
 
 // kernels.hip
 hipError_t launch_leaf_inverse(const double* A, int64_t lda, double* P, int64_t ldp, int b, int64_t row0,
@@ -73,9 +82,7 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
                             double* R, int64_t ldr, hipStream_t s, double* flops);
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
                         int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
-hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s);
-hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, int bmax, int mmax, hipStream_t s);
-hipError_t launch_schur_batched(const StepArgs* args, int64_t count, int mmax, hipStream_t s);
+hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s);
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);

@@ -244,13 +244,6 @@ __global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restr
   leaf_body<RPL, CPW, NWV>(A, lda, P, ldp, b, row0, info);
 }
 
-// Batched leaf: workgroup i inverts jobs[i].
-
-template <int RPL, int CPW, int NWV>
-__global__ void __launch_bounds__(64 * NWV) k_leaf_inverse_batched(const LeafJob* __restrict__ jobs) {
-  const LeafJob j = jobs[blockIdx.x];
-  leaf_body<RPL, CPW, NWV>(j.A, j.lda, j.P, j.ldp, j.b, (int64_t)j.row0, j.info);
-}
 
 // ---------------------------------------------------------------------------
 // Column panel save: Ct[t][i] = W[i][o + t], t < b, i < n (tiled transpose).
@@ -569,43 +562,6 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g) {
   }
 }
 
-// Batched form: workgroup i runs every tile of problem args[i] (one small
-// matrix of a batch).  For the Schur update the workgroup first copies the old
-// column panel W[:, o:o+b] (from Win) row-major into g.A (ld g.lda = b), which
-// is then the m-major contraction operand.
-template <int MODE, class C, bool A_KMAJOR>
-// Workgroup (job, y): row panel: tile y of the job; Schur update: tile-row y
-// of the job.  A Schur tile-row reads and writes only its own rows of W, so
-// its workgroup first copies those rows' old column panel W[rows, o:o+b] into
-// the job's Ct (m-major, ld = b) and then updates the row's tiles, the
-// block-p columns included; no other workgroup touches those rows.
-__global__ void __launch_bounds__(C::NT) k_gemm_step_batched(const StepArgs* __restrict__ args) {
-  __shared__ double As[2][C::BK * C::LA];
-  __shared__ double Bs[2][C::BK * C::LB];
-  const StepArgs g = args[blockIdx.x];
-  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
-  if (MODE == MODE_SCHUR) {
-    const int64_t tm = blockIdx.y;
-    if (tm >= TM) return;
-    double* Cp = const_cast<double*>(g.A);
-    const int64_t r0 = tm * C::BM;
-    const int64_t rows = (g.M - r0 < C::BM) ? g.M - r0 : C::BM;
-    const int total = (int)rows * g.b;  // <= 64 x 128
-    for (int e = threadIdx.x; e < total; e += C::NT) {
-      const int q = e / g.b;
-      const int t = e - q * g.b;
-      const int64_t i = r0 + q;
-      Cp[i * g.lda + t] = g.Win[i * g.ldwin + g.o + t];
-    }
-    __syncthreads();
-    for (int64_t tn = 0; tn < TN; ++tn) gemm_tile<MODE, C, A_KMAJOR, false>(g, tm, tn, As, Bs);
-  } else {
-    const int64_t t = blockIdx.y;
-    if (t >= TM * TN) return;
-    gemm_tile<MODE, C, A_KMAJOR, false>(g, t / TN, t % TN, As, Bs);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from the C ABI implementation).
 // ---------------------------------------------------------------------------
@@ -801,35 +757,51 @@ hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int6
   return launch_step<MODE_RESID, 64, 64, false>(g, s, 0, 0, 0, nullptr);
 }
 
-hipError_t launch_leaf_batched(const LeafJob* jobs, int64_t count, int bmax, hipStream_t s) {
+// ---------------------------------------------------------------------------
+// One batched sweep step of one matrix per workgroup: P = W_pp^-1 (leaf), the
+// row panel R = P W[p, :], the old column panel W[:, p] copied to Ct, then the
+// Schur update of every tile.  The workgroup alone touches this matrix during
+// the launch, so the phases only need workgroup barriers; the arithmetic is
+// that of the separate leaf, row-panel and Schur launches.
+// ---------------------------------------------------------------------------
+template <int RPL, int CPW, int NWV, class C>
+__global__ void __launch_bounds__(64 * NWV) k_swept_step(const SweptJob* __restrict__ jobs) {
+  static_assert(64 * NWV == C::NT, "leaf and tile shapes must use the same workgroup");
+  __shared__ double As[2][C::BK * C::LA];
+  __shared__ double Bs[2][C::BK * C::LB];
+  const SweptJob& J = jobs[blockIdx.x];
+  leaf_body<RPL, CPW, NWV>(J.leaf.A, J.leaf.lda, J.leaf.P, J.leaf.ldp, J.leaf.b, (int64_t)J.leaf.row0, J.leaf.info);
+  __syncthreads();
+  {
+    const StepArgs& g = J.row;
+    const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
+    for (int64_t t = 0; t < TM * TN; ++t) gemm_tile<MODE_ROW, C, false, false>(g, t / TN, t % TN, As, Bs);
+  }
+  __syncthreads();
+  {
+    const StepArgs& g = J.schur;
+    double* Cp = const_cast<double*>(g.A);
+    const int total = (int)g.M * g.b;  // <= 256 x 128
+    for (int e = threadIdx.x; e < total; e += C::NT) {
+      const int i = e / g.b;
+      const int t = e - i * g.b;
+      Cp[(int64_t)i * g.lda + t] = g.Win[(int64_t)i * g.ldwin + g.o + t];
+    }
+    __syncthreads();
+    const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
+    for (int64_t t = 0; t < TM * TN; ++t) gemm_tile<MODE_SCHUR, C, false, false>(g, t / TN, t % TN, As, Bs);
+  }
+}
+
+hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const dim3 g((unsigned)count);
-  if (bmax <= 16)
-    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 4, 4>), g, dim3(256), 0, s, jobs);
-  else if (bmax <= 32)
-    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 8, 4>), g, dim3(256), 0, s, jobs);
-  else if (bmax <= 64)
-    hipLaunchKernelGGL((k_leaf_inverse_batched<1, 16, 4>), g, dim3(256), 0, s, jobs);
+  if (bmax <= 64)
+    hipLaunchKernelGGL((k_swept_step<1, 16, 4, TileCfg<64, 64, 2, 2>>), dim3((unsigned)count), dim3(256), 0, s, jobs);
   else
-    hipLaunchKernelGGL((k_leaf_inverse_batched<2, 16, 8>), g, dim3(512), 0, s, jobs);
+    hipLaunchKernelGGL((k_swept_step<2, 16, 8, TileCfg<64, 64, 4, 2>>), dim3((unsigned)count), dim3(512), 0, s, jobs);
   return hipGetLastError();
 }
 
-// bmax, mmax: the largest block and matrix order among the jobs (they size
-// the second grid dimension; surplus workgroups return at once).
-hipError_t launch_row_panel_batched(const StepArgs* args, int64_t count, int bmax, int mmax, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  const unsigned tiles = (unsigned)(((bmax + 63) / 64) * ((mmax + 63) / 64));
-  hipLaunchKernelGGL((k_gemm_step_batched<MODE_ROW, TileCfg<64, 64, 2, 2>, false>), dim3((unsigned)count, tiles),
-                     dim3(256), 0, s, args);
-  return hipGetLastError();
-}
 
-hipError_t launch_schur_batched(const StepArgs* args, int64_t count, int mmax, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gemm_step_batched<MODE_SCHUR, TileCfg<64, 64, 2, 2>, false>),
-                     dim3((unsigned)count, (unsigned)((mmax + 63) / 64)), dim3(256), 0, s, args);
-  return hipGetLastError();
-}
 
 }  // namespace binv

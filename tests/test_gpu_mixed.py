@@ -123,3 +123,13 @@ def test_full_size_mixed_configuration(gpu):
     An = A.cpu().numpy()
     Xn = X.cpu().numpy()
     assert oracle.residual_stats(An, Xn, rows)["rho"] <= 1e-10
+
+
+def test_mixed_degenerate_orders(gpu):
+    """n = 0 returns at once; n = 1 is exact."""
+    import torch
+    from paper_2305_11103_amd import binv
+    X, info = binv.invert_mixed(torch.zeros((0, 0), dtype=torch.float64, device="cuda"))
+    assert X.shape == (0, 0) and info["converged"]
+    X1, info1 = binv.invert_mixed(torch.tensor([[4.0]], dtype=torch.float64, device="cuda"))
+    assert float(X1[0, 0]) == 0.25 and info1["converged"]

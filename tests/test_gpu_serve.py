@@ -138,3 +138,21 @@ def test_completion_queue_returns_every_ticket_once(gpu):
     assert srv.next_done() is None
     assert isinstance(first[tickets[0]], tuple)
     srv.close()
+
+
+def test_order_one_and_edge_orders(gpu):
+    """Orders 1, 128, 129 (the small/large boundary) and 4096 (the large lane)
+    through the server, against the oracle."""
+    from paper_2305_11103_amd import binv
+    srv = binv.Server(hbm_budget=4 << 30)
+    mats = [np.array([[8.0]]), wl.spd_gram(128, 1), wl.spd_gram(129, 2), wl.diag_dominant(4096, 3)]
+    tickets = [srv.submit(A) for A in mats]
+    res = wait_all(srv, tickets, timeout=300)
+    for A, t in zip(mats, tickets):
+        X = res[t][0]
+        if A.shape[0] == 1:
+            assert X[0, 0] == 0.125
+        else:
+            rows = np.arange(0, A.shape[0], max(1, A.shape[0] // 64))
+            assert oracle.residual_stats(A, X, rows)["rho"] <= 1e-10
+    srv.close()
