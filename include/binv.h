@@ -202,7 +202,8 @@ binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, in
  * later on that context start from it.  Synchronous.  chosen (may be NULL):
  * int32[5], the shape index per tier (-1 for an empty tier); ms (may be
  * NULL): double[5 * 4], the best time of each (tier, shape), 0 when not run
- * (tiers have 4, 4, 4, 4 and 2 shapes). */
+ * (tiers have 4, 4, 4, 4 and 3 shapes; the last tier's third shape is its
+ * first compiled for two workgroups per CU). */
 binv_status binv_batch_tune(binv_batch* plan, const double* A, double* X, int32_t* d_info, int32_t reps,
                             void* stream, int32_t* chosen, double* ms);
 

@@ -40,7 +40,7 @@ BINV_F_SAMPLED_CHECK = 16
 BINV_SERVER_STRICT_PRECISION = 1
 BINV_SERVER_FULL_CHECK = 2
 PHASES = ("pivot", "row", "schur", "other", "band", "small")
-TIER_SHAPES = (4, 4, 4, 4, 2)  # launch shapes per register tier (autotuned)
+TIER_SHAPES = (4, 4, 4, 4, 3)  # launch shapes per register tier (autotuned)
 
 
 class BinvError(RuntimeError):

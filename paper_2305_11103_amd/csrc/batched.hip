@@ -75,8 +75,10 @@ __device__ __forceinline__ void small_search(const double (&x)[RPL], const bool 
   }
 }
 
-template <int RPL, int CPW, int NWV, int SUB>
-__global__ void __launch_bounds__(64 * NWV * SUB)
+// MINW: waves per SIMD the register budget must allow (1 = no constraint;
+// 4 lets two 8-wave workgroups share a CU at the cost of a few spilled bytes).
+template <int RPL, int CPW, int NWV, int SUB, int MINW = 1>
+__global__ void __launch_bounds__(64 * NWV * SUB) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const SmallMat* __restrict__ mats,
                 const int32_t* __restrict__ order, int64_t count, const int32_t* __restrict__ bounds,
                 int32_t* __restrict__ info) {
@@ -359,16 +361,16 @@ static const TierShape kShapes[5][kSmallVariants] = {
     {{1, 16, 1, 4}, {1, 16, 1, 8}, {1, 8, 2, 4}, {1, 8, 2, 2}},     // m <= 16
     {{1, 32, 1, 4}, {1, 16, 2, 2}, {1, 8, 4, 1}, {1, 32, 1, 8}},    // m <= 32
     {{1, 16, 4, 1}, {1, 32, 2, 2}, {1, 8, 8, 1}, {1, 16, 4, 2}},    // m <= 64
-    {{2, 16, 8, 1}, {2, 8, 16, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},     // m <= 128 (wider shapes spill)
-};
-static const int kShapeCount[5] = {4, 4, 4, 4, 2};
+    {{2, 16, 8, 1}, {2, 8, 16, 1}, {2, 16, 8, 1}, {0, 0, 0, 0}},    // m <= 128 (wider shapes spill);
+};                                                                  // shape 2 = shape 0 at two workgroups per CU
+static const int kShapeCount[5] = {4, 4, 4, 4, 3};
 
-template <int RPL, int CPW, int NWV, int SUB>
+template <int RPL, int CPW, int NWV, int SUB, int MINW = 1>
 hipError_t launch_shape(const double* A, double* X, const SmallMat* mats, const int32_t* order, int64_t count,
                         const int32_t* bounds, int32_t* info, hipStream_t s) {
   const unsigned g = (unsigned)((count + SUB - 1) / SUB);
-  hipLaunchKernelGGL((k_small_inverse<RPL, CPW, NWV, SUB>), dim3(g), dim3(64 * NWV * SUB), 0, s, A, X, mats, order,
-                     count, bounds, info);
+  hipLaunchKernelGGL((k_small_inverse<RPL, CPW, NWV, SUB, MINW>), dim3(g), dim3(64 * NWV * SUB), 0, s, A, X, mats,
+                     order, count, bounds, info);
   return hipGetLastError();
 }
 
@@ -384,6 +386,7 @@ hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, 
   BINV_SHAPE(2, 0, 1, 32, 1, 4) BINV_SHAPE(2, 1, 1, 16, 2, 2) BINV_SHAPE(2, 2, 1, 8, 4, 1) BINV_SHAPE(2, 3, 1, 32, 1, 8)
   BINV_SHAPE(3, 0, 1, 16, 4, 1) BINV_SHAPE(3, 1, 1, 32, 2, 2) BINV_SHAPE(3, 2, 1, 8, 8, 1) BINV_SHAPE(3, 3, 1, 16, 4, 2)
   BINV_SHAPE(4, 0, 2, 16, 8, 1) BINV_SHAPE(4, 1, 2, 8, 16, 1)
+  if (tier == 4 && variant == 2) return launch_shape<2, 16, 8, 1, 4>(A, X, mats, order, count, bounds, info, s);
 #undef BINV_SHAPE
   return hipErrorInvalidValue;
 }
