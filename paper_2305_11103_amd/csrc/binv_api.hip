@@ -120,7 +120,6 @@ binv_status ensure_side(binv_ctx* c) {
     const int v = e ? atoi(e) : kReserveCUs;
     return (v >= 8 && v <= 64) ? v / 8 * 8 : kReserveCUs;
   }();
-  c->nreserved = nres;
   std::vector<char> reserved(c->ncu, 0);
   const int span = std::max(1, c->ncu / 8);
   for (int x = 0; x < 8; ++x)
@@ -147,20 +146,6 @@ binv_status ensure_side(binv_ctx* c) {
   HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_gemm, hipEventDisableTiming));
   return BINV_OK;
-}
-
-// Workgroups of the trailing update under lookahead.  0: one per tile, dealt
-// out while the kernel runs (default); otherwise a persistent grid of two per
-// CU of the trailing-update stream.  The persistent grid measured slower for
-// both the trailing update (48.5 against 51.5 TFLOP/s) and the side stream's
-// pivot chain.  BINV_REST_SLOTS: 0 = one per tile, 1 = persistent.
-int rest_slots(const binv_ctx* c) {
-  static const int mode = [] {
-    const char* e = getenv("BINV_REST_SLOTS");
-    return e ? atoi(e) : 0;
-  }();
-  if (mode == 0) return 0;
-  return 2 * (c->ncu - c->nreserved);
 }
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
@@ -218,7 +203,7 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
       {
         PhaseTimer t(c, level, BINV_PHASE_SCHUR, c->gemm);
         HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->gemm,
-                                   t.fl(), rest_slots(c)));
+                                   t.fl(), 0));
       }
       HIP_TRY(hipEventRecord(c->ev_gemm, c->gemm));
       HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));

@@ -171,7 +171,6 @@ struct Level {
 struct binv_ctx {
   int device = 0;
   int ncu = 256;  // compute units of the device
-  int nreserved = 8;  // CUs of the lookahead side stream
   binv::Level lv[2];
   binv::DevBuf info;  // scratch info word when the caller passes none
   // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few

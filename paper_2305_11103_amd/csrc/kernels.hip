@@ -349,10 +349,8 @@ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64
 template <int BM_, int BN_, int NWM_, int NWN_>
 struct TileCfg {
   static constexpr int BM = BM_, BN = BN_, NWM = NWM_, NWN = NWN_;
-  // waves per SIMD the register budget is sized for: two workgroups per CU
-  // for 128x128 tiles, one for the larger ones (whose accumulators need 128
-  // VGPRs per lane)
-  static constexpr int WPE = (BM_ * BN_ > 128 * 128) ? 2 : ((64 * NWM_ * NWN_ >= 512) ? 4 : 2);
+  // waves per SIMD the register budget is sized for (two workgroups per CU)
+  static constexpr int WPE = (64 * NWM_ * NWN_ >= 512) ? 4 : 2;
   static constexpr int NT = 64 * NWM * NWN;
   static constexpr int BK = 16;
   static constexpr int PAD = 4;
@@ -714,16 +712,7 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
     const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
     return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0);
   }
-  if (schur_tile(n) == 128) {
-    static const int cfg = [] {
-      const char* e = getenv("BINV_SCHUR_CFG");
-      return e ? atoi(e) : 1;
-    }();
-    if (cfg == 1) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
-    if (cfg == 2) return launch_step<MODE_SCHUR, 256, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
-    if (cfg == 3) return launch_step<MODE_SCHUR, 128, 256, true, 2, 4>(g, s, region, qo, qb, flops, slots);
-    return launch_step<MODE_SCHUR, 128, 128, true, 2, 2>(g, s, region, qo, qb, flops, slots);
-  }
+  if (schur_tile(n) == 128) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);
 }
 
