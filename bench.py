@@ -466,8 +466,9 @@ def bench_serve(args):
         return b
 
     # Serial FIFO capacity, one request at a time: the plain FP64 sweep alone,
-    # and the same sweep followed by the server's residual check (64 sampled
-    # rows; refinement when it fails), i.e. at the accuracy the server gives.
+    # and the same sweep followed by the server's residual check (the random-
+    # probe estimate; refinement when it fails), i.e. at the accuracy the server
+    # gives.
     log(f"bench: serial plain-FP64 baseline over {N} requests")
     t_plain = t_checked = 0.0
     X_full = torch.empty(int(sizes.max()) ** 2, dtype=torch.float64, device=dev)
@@ -553,13 +554,18 @@ def bench_serve(args):
         # accuracy on the oracle-checked requests: the gate is the target, or
         # twice the oracle Gauss-Jordan inverse's own rho where that is larger
         rhos = {"fp64": [], "mixed": []}
-        worst = 0.0
+        worst, worst_req = 0.0, None
         for i, v in keep.items():
             A, X, info = v
             r = oracle.residual_stats(A, X)["rho"]
             r_o1 = oracle.residual_stats(A, oracle.gj_inverse(A))["rho"]
             rhos[str(tags[i])].append(r)
-            worst = max(worst, r / max(1e-10, 2.0 * r_o1))
+            q = r / max(1e-10, 2.0 * r_o1)
+            if q >= worst:
+                worst = q
+                worst_req = {"request": int(i), "n": int(sizes[i]), "cond": float(conds[i]), "tag": str(tags[i]),
+                             "rho_oracle": r, "rho_oracle_gj": r_o1, "rho_device": info["rho"],
+                             "estimated": bool(info["sampled"]), "refine_steps": int(info["refine_steps"])}
         p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
         log(f"bench: {label}: {N / makespan:.1f} solves/s, {flops / makespan / 1e12:.2f} TFLOP/s, "
             f"p50 {p50:.2f} ms, p99 {p99:.2f} ms, peak {peak / 2**30:.1f} GiB")
@@ -568,7 +574,7 @@ def bench_serve(args):
                 "peak_charged_bytes": int(peak), "oracle_checked": len(keep),
                 "rho_max_fp64_sampled": max(rhos["fp64"]) if rhos["fp64"] else None,
                 "rho_max_mixed_sampled": max(rhos["mixed"]) if rhos["mixed"] else None,
-                "worst_rho_over_gate": worst, "not_converged": not_conv}
+                "worst_rho_over_gate": worst, "worst_request": worst_req, "not_converged": not_conv}
 
     served = run(mu, f"served at lambda={mu:.1f}/s")
     sat = run(0, "saturation")

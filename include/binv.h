@@ -69,10 +69,10 @@ typedef enum {
 #define BINV_F_REFINE_FROM_FP64 8u /* binv_invert_mixed: start the refinement from
                              the plain FP64 sweep instead of the FP32 one */
 #define BINV_F_SAMPLED_CHECK 16u /* binv_invert_mixed: accept an iterate on
-                             rho estimated from 64 evenly spaced rows of
-                             I - A X (2 * 64 * n^2 flops instead of 2 n^3);
-                             the full residual is formed only when a
-                             Newton-Schulz step needs it */
+                             rho estimated from 64 random sign probes (see
+                             binv_residual; 4 * 64 * n^2 flops instead of
+                             2 n^3) for n >= 192; the full residual is formed
+                             only when a Newton-Schulz step needs it */
 #define BINV_F_GRAPH 4u  /* batched calls: capture the whole launch sequence in
                              a HIP graph on first use and replay it (re-captured
                              when the A, X or info pointers change) */
@@ -136,9 +136,24 @@ typedef struct {
                               would not converge), so the FP64 sweep was used
                               as the starting point */
   int32_t converged;       /* 1: rho <= target */
-  int32_t sampled;         /* 1: rho is the sampled-rows estimate
+  int32_t sampled;         /* 1: rho is the random-probe estimate
                               (BINV_F_SAMPLED_CHECK); 0: the full residual */
 } binv_info;
+
+/* rho = ||A X - I||_F / sqrt(n) of a given X: the residual norm check (a6 of
+ * the hot path) on its own, A and X FP64 row-major on ctx's device.  flags 0:
+ * the full residual I - A X (an n x n x n FP64 GEMM, 2 n^3 flops) and its
+ * norm.  BINV_RESID_ESTIMATE: the mean of ||(A X - I) z||^2 over 64 random
+ * sign vectors z (Hutchinson's estimator of the squared Frobenius norm, as
+ * A (X z) - z: two n x n x 64 products), an unbiased estimate of rho^2 whose
+ * relative standard deviation is at most sqrt(2/64) however the error is
+ * spread over the rows; orders below 192 always take the full residual.  The
+ * probes are a fixed function of n, so equal inputs give equal results.
+ * Uses ctx's workspace (n^2 doubles); synchronizes `stream` and writes *rho.
+ * Errors: BINV_E_INVALID (NULL pointers, n < 0, ld < n, unknown flags). */
+#define BINV_RESID_ESTIMATE 1u
+binv_status binv_residual(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
+                          uint32_t flags, void* stream, double* rho);
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
  * is read again by the refinement.  opts: the partition (as binv_invert) and
@@ -240,8 +255,8 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * Every request of order > 128 ends with the FP64 residual check against its
  * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
- * fails; the check asks for half the target (it carries rounding and
- * sampling error of its own), info->converged reports rho <= target.
+ * fails; the check asks for half the target (it carries rounding error and,
+ * as an estimate, a spread of its own), info->converged reports rho <= target.
  * BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
  * the FP32 sweep under the policy of BINV_SERVER_STRICT_PRECISION below.
  * Requests of order <= 128 are inverted in FP64 (Gauss-Jordan with pivoting

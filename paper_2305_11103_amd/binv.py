@@ -28,7 +28,7 @@ BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
-           "binv_invert_mixed",
+           "binv_invert_mixed", "binv_residual",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
            "binv_server_create", "binv_submit", "binv_poll", "binv_next_done", "binv_server_stats",
@@ -37,6 +37,7 @@ EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "bin
 BINV_F_GRAPH = 4
 BINV_F_REFINE_FROM_FP64 = 8
 BINV_F_SAMPLED_CHECK = 16
+BINV_RESID_ESTIMATE = 1
 BINV_SERVER_STRICT_PRECISION = 1
 BINV_SERVER_FULL_CHECK = 2
 PHASES = ("pivot", "row", "schur", "other", "band", "small")
@@ -85,6 +86,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise OSError(f"{LIB_PATH} is missing: build it with paper_2305_11103_amd._build.build_library()")
+    # torch ships its own HIP runtime; loading torch first makes the library
+    # bind to that same runtime (its soname satisfies the library's), so the
+    # tensors and streams passed in belong to the runtime the library calls.
+    # Loaded the other way round, the process would hold two runtimes.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     lib.binv_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
@@ -101,6 +107,9 @@ def load_library():
     lib.binv_invert_mixed.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts),
                                       ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(_Info)]
     lib.binv_invert_mixed.restype = ctypes.c_int
+    lib.binv_residual.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_uint32, P,
+                                  ctypes.POINTER(ctypes.c_double)]
+    lib.binv_residual.restype = ctypes.c_int
     lib.binv_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint32,
                                        ctypes.POINTER(P)]
     lib.binv_server_create.restype = ctypes.c_int
@@ -293,6 +302,29 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
     k = inf.refine_steps
     return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1 + inf.fell_back]), "refine_steps": k,
                "fell_back": bool(inf.fell_back), "converged": bool(inf.converged), "sampled": inf.sampled}
+
+
+def residual(A, X, estimate=False, ctx=None):
+    """rho = ||AX - I||_F / sqrt(n) on the GPU: the full FP64 residual, or with
+    estimate=True its 64-probe random-sign estimate (exact below order 192)."""
+    import torch
+
+    for M, nm in ((A, "A"), (X, "X")):
+        if M.dim() != 2 or M.dtype != torch.float64 or not M.is_cuda or M.stride(1) != 1:
+            raise ValueError(f"{nm} must be a row-major float64 CUDA matrix")
+    n = A.shape[0]
+    if A.shape != (n, n) or X.shape != (n, n) or A.device != X.device:
+        raise ValueError("A and X must be square, of one order, on one device")
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or default_context(dev)
+    rho = ctypes.c_double()
+    with torch.cuda.device(dev):
+        st = load_library().binv_residual(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
+                                          ctypes.c_void_p(X.data_ptr()), max(X.stride(0), n, 1),
+                                          BINV_RESID_ESTIMATE if estimate else 0, _stream_handle(torch, dev),
+                                          ctypes.byref(rho))
+    _check(st)
+    return rho.value
 
 
 def batch_shape(tier, shape):

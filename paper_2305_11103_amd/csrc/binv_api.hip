@@ -343,20 +343,30 @@ binv_status residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, 
   return BINV_OK;
 }
 
-// rho estimated from rows 0, t, 2t, ... (t = n / 64) of I - A X: the mean
-// squared row norm of the sample stands in for ||I - A X||_F^2 / n.
-constexpr int64_t kSampleRows = 64;
-binv_status sampled_residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X,
-                                  int64_t ldx, double* Res, hipStream_t s, double* rho) {
-  const int64_t rows = std::min<int64_t>(n, kSampleRows);
-  const int64_t stride = n / rows;
-  HIP_TRY(binv::launch_resid_rows(A, lda, X, ldx, Res, n, rows, stride, s));
+// rho estimated from kProbes random sign vectors z: the mean of
+// ||(A X - I) z||^2 over the probes is an unbiased estimate of ||A X - I||_F^2
+// with relative standard deviation at most sqrt(2 / kProbes) = 0.18 however
+// the error is spread over the rows (a sample of rows is not: where a few rows
+// carry most of the error it can miss them).  It costs two n x n x kProbes
+// products (4 kProbes n^2 flops) instead of the full residual's 2 n^3.  Res
+// needs 3 kProbes n doubles, which the n^2 of the full residual cover once
+// n >= kProbeMinN; below that the full residual is cheaper anyway.
+constexpr int kProbes = 64;
+constexpr int64_t kProbeMinN = 3 * kProbes;
+constexpr uint64_t kProbeSeed = 0x243F6A8885A308D3ull;
+
+binv_status probe_residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
+                                double* Res, hipStream_t s, double* rho) {
+  double* Z = Res;
+  double* Zn = Res + (int64_t)kProbes * n;
+  double* Y = Res + 2 * (int64_t)kProbes * n;
+  HIP_TRY(binv::launch_probe_residual(A, lda, X, ldx, n, kProbes, Z, Zn, Y, kProbeSeed ^ (uint64_t)n, s));
   double* part = (double*)c->mx_part.p;
-  HIP_TRY(binv::launch_sumsq(Res, n, rows, n, part, part + binv::kSumPartsHost, s));
+  HIP_TRY(binv::launch_sumsq(Z, kProbes, n, kProbes, part, part + binv::kSumPartsHost, s));
   double h = 0.0;
   HIP_TRY(hipMemcpyAsync(&h, part + binv::kSumPartsHost, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *rho = std::sqrt(h / (double)rows);
+  *rho = std::sqrt(h / ((double)kProbes * (double)n));
   return BINV_OK;
 }
 
@@ -418,6 +428,31 @@ binv_status sweep_f32(binv_ctx* c, int64_t n, const double* A, int64_t lda, doub
 
 extern "C" {
 
+binv_status binv_residual(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
+                          uint32_t flags, void* stream, double* rho) {
+  if (!ctx || !rho) return fail(BINV_E_INVALID, "ctx or rho is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (flags & ~BINV_RESID_ESTIMATE) return fail(BINV_E_INVALID, "unknown flags");
+  *rho = 0.0;
+  if (n == 0) return BINV_OK;
+  if (!A || !X) return fail(BINV_E_INVALID, "A or X is NULL");
+  if (lda < n || ldx < n) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const bool estimate = (flags & BINV_RESID_ESTIMATE) && n >= kProbeMinN;
+  binv_status st = ctx->mx_res.ensure(sizeof(double) * (size_t)n * (size_t)n);
+  if (st == BINV_OK) st = ctx->mx_part.ensure(sizeof(double) * (binv::kSumPartsHost + 1));
+  if (st == BINV_OK) {
+    double* Res = (double*)ctx->mx_res.p;
+    st = estimate ? probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho)
+                  : residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho);
+  }
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
 binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
                               const binv_opts* opts, double target, int32_t max_refine, void* stream,
                               binv_info* info_out) {
@@ -469,7 +504,8 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
   {
     const bool look = !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD));
     const bool from64 = opts && (opts->flags & BINV_F_REFINE_FROM_FP64);
-    const bool sampled = opts && (opts->flags & BINV_F_SAMPLED_CHECK);
+    // small orders take the full residual, which is as cheap as the estimate there
+    const bool sampled = opts && (opts->flags & BINV_F_SAMPLED_CHECK) && n >= kProbeMinN;
     if (from64) {
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
@@ -480,9 +516,9 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
     if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
     if (sampled) {
-      // accept the sweep on the sampled estimate when it already meets the target
+      // accept the sweep on the estimate when it already meets the target
       double est = 0.0;
-      if ((st = sampled_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
+      if ((st = probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
       if (est <= target) {
         inf.rho_steps[0] = est;
         inf.rho = est;
@@ -518,7 +554,7 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
       const double prev_rho = rho;
       if (sampled) {
         double est = 0.0;
-        if ((st = sampled_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
+        if ((st = probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
         if (est <= target) {
           if (hk < 8) inf.rho_steps[hk++] = est;
           inf.rho = est;

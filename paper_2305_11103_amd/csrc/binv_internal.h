@@ -36,7 +36,6 @@ struct StepArgs {
   int region;
   int64_t tr0, tr1, tc0, tc1;
   int64_t ntiles;     // tiles enumerated by the region (before band skipping)
-  int64_t dstride;    // residual: output row i holds row i * dstride of I - A B
 };
 
 // One small matrix of a batch.
@@ -86,8 +85,8 @@ hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipS
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);
-hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int64_t ldx, double* R, int64_t n,
-                             int64_t rows, int64_t stride, hipStream_t s);
+hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n, int k,
+                                 double* Z, double* Zn, double* Y, uint64_t seed, hipStream_t s);
 constexpr int kModeResid = 2;  // C = I - A B
 constexpr int kModeAdd = 3;    // C = Cin + A B
 

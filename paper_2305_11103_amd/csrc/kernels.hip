@@ -286,6 +286,21 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t* p, int64_t n, int32_t
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
 
+// Random sign probes of the residual estimate: Z[e] = +-1 and Zn[e] = -Z[e]
+// for e < count, the sign being the top bit of SplitMix64 (Steele, Lea and
+// Flood, 2014) at position seed + e.
+__global__ void __launch_bounds__(256) k_sign_probes(double* Z, double* Zn, int64_t count, uint64_t seed) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+    uint64_t x = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    const double v = (x >> 63) ? 1.0 : -1.0;
+    Z[e] = v;
+    Zn[e] = -v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // GEMM step kernel.
 // ---------------------------------------------------------------------------
@@ -525,7 +540,7 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
       if (j >= g.N) continue;
       const bool jp = (j >= o && j < o + b);
       if (MODE == MODE_RESID) {
-        g.W[i * g.ldw + j] = (i * g.dstride == j ? 1.0 : 0.0) - acc[r][c];
+        g.W[i * g.ldw + j] = (i == j ? 1.0 : 0.0) - acc[r][c];
       } else if (MODE == MODE_ADD) {
         g.W[i * g.ldw + j] = g.Win[i * g.ldwin + j] + acc[r][c];
       } else if (MODE == MODE_ROW) {
@@ -727,23 +742,39 @@ hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double*
   g.Win = Cin; g.ldwin = ldcin;
   g.R = nullptr; g.ldr = 0;
   g.M = n; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
-  g.dstride = 1;
   if (mode == MODE_RESID) return launch_step<MODE_RESID, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
   return launch_step<MODE_ADD, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
 }
 
-// Rows 0, stride, 2 stride, ... (`rows` of them) of I - A X into R (rows x n,
-// ld = n): A's sampled rows are read with leading dimension lda * stride.
-hipError_t launch_resid_rows(const double* A, int64_t lda, const double* X, int64_t ldx, double* R, int64_t n,
-                             int64_t rows, int64_t stride, hipStream_t s) {
+// The probed residual E = Z - A X Z (n x k, ld = k) for k random sign
+// columns Z: Z and Zn = -Z are drawn into Z and Zn, Y = X Zn, then E = Z + A Y
+// in place of Z.  Every row of A X - I contributes to every column of E, so
+// the mean of ||E[:, j]||^2 over the probes is an unbiased estimate of
+// ||A X - I||_F^2 whatever the distribution of the error over the rows.
+hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n, int k,
+                                 double* Z, double* Zn, double* Y, uint64_t seed, hipStream_t s) {
+  if (n <= 0 || k <= 0) return hipSuccess;
+  const int64_t count = n * k;
+  const int64_t gz = (count + 255) / 256;
+  hipLaunchKernelGGL(k_sign_probes, dim3((unsigned)(gz < 1024 ? gz : 1024)), dim3(256), 0, s, Z, Zn, count, seed);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   StepArgs g;
   std::memset(&g, 0, sizeof(g));
-  g.A = A; g.lda = lda * stride;
-  g.B = X; g.ldb = ldx;
-  g.W = R; g.ldw = n;
-  g.M = rows; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
-  g.dstride = stride;
-  return launch_step<MODE_RESID, 64, 64, false>(g, s, 0, 0, 0, nullptr);
+  // Y = X Zn: the row-panel product with an empty block (no copied columns)
+  g.A = X; g.lda = ldx;
+  g.B = Zn; g.ldb = k;
+  g.W = Y; g.ldw = k;
+  g.M = n; g.N = k; g.K = (int)n; g.o = 0; g.b = 0;
+  if ((e = launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, nullptr)) != hipSuccess) return e;
+  // E = Z + A Y, in place
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda;
+  g.B = Y; g.ldb = k;
+  g.W = Z; g.ldw = k;
+  g.Win = Z; g.ldwin = k;
+  g.M = n; g.N = k; g.K = (int)n; g.o = 0; g.b = 0;
+  return launch_step<MODE_ADD, 64, 64, false>(g, s, 0, 0, 0, nullptr);
 }
 
 // ---------------------------------------------------------------------------

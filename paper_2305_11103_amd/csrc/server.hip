@@ -39,9 +39,10 @@ constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WOR
 constexpr int kMaxRoundSmall = 65536;
 constexpr int64_t kBigN = 4096;    // orders served one at a time on worker 0
 constexpr double kFp32Reach = 1e-6;  // rho the FP32 sweep can meet without refinement
-// The device's check (an FP64 residual, or its 64-row estimate) carries its
-// own rounding and sampling error of the order of the rho it measures near
-// 1e-10, so a request is refined until that check reads half its target.
+// The device's check (an FP64 residual, or its random-probe estimate) carries
+// its own rounding error, and the estimate a spread, of the order of the rho
+// it measures near 1e-10, so a request is refined until that check reads half
+// its target.
 constexpr double kCheckMargin = 0.5;
 
 double now_s() {
@@ -406,8 +407,8 @@ void worker_main(binv_server* s, int w) {
     // lane only; mid-size sweeps overlap each other instead
     o.flags = BINV_F_SYNC | (r->n < kBigN ? BINV_F_NO_LOOKAHEAD : 0u);
     // Every request ends with the FP64 residual check against its target
-    // (sampled rows unless BINV_SERVER_FULL_CHECK) and is refined only if the
-    // check fails.  An FP64 request starts from the FP64 sweep.  A mixed
+    // (the random-probe estimate unless BINV_SERVER_FULL_CHECK) and is refined
+    // only if the check fails.  An FP64 request starts from the FP64 sweep.  A mixed
     // request starts from the FP32 sweep when its target is within that
     // sweep's reach or the server honours tags strictly; otherwise one
     // Newton-Schulz step (two FP64 GEMMs of the sweep's size) would cost more

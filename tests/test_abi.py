@@ -53,3 +53,19 @@ def test_tier_shape_table():
             assert 64 * nwv * sub <= 1024
         with pytest.raises(binv.BinvError):
             binv.batch_shape(t, count)
+
+
+def test_binding_shares_torch_hip_runtime():
+    """Loading the library through the binding, before anything imports
+    torch, maps a single HIP runtime: torch's (it ships its own copy)."""
+    import subprocess
+    import sys
+    code = ("from paper_2305_11103_amd import binv\n"
+            "binv.load_library()\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    import ast
+    libs = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1 and "torch" in libs[0], libs

@@ -78,8 +78,8 @@ def test_mixed_singular(gpu):
 
 def test_sampled_check_accepts_an_accurate_sweep(gpu):
     """BINV_F_SAMPLED_CHECK: an FP64 sweep that already meets the target is
-    accepted on the 64-row estimate (no refinement, X bitwise equal to the
-    plain sweep), and the estimate tracks the oracle's full residual."""
+    accepted on the random-probe estimate (no refinement, X bitwise equal to
+    the plain sweep), and the estimate tracks the oracle's full residual."""
     import torch
     from paper_2305_11103_amd import binv
     n = 640
