@@ -128,7 +128,10 @@ def bench_plain(args):
         torch.cuda.synchronize()
         log(f"bench: warmup {i + 1}/{args.warmup} done")
 
-    ctx.set_timing(["schur", "band", "pivot", "row"])
+    # Only the trailing-update launches (on their own stream) carry timing
+    # events in the timed region: event pairs on the caller's stream would add
+    # their own gaps to the step being measured.
+    ctx.set_timing(["schur"])
     ctx.get_timing()  # discard anything pending
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -141,10 +144,17 @@ def bench_plain(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     timing = ctx.get_timing()
-    ctx.set_timing([])
     per = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
     ms_step = wall * 1e3 / args.steps
     log(f"bench: {args.steps} steps in {wall:.3f} s ({ms_step:.3f} ms/step)")
+    # phase breakdown from one more step, outside the timed region, with every
+    # phase's launches bracketed by events
+    ctx.set_timing(["schur", "band", "pivot", "row", "tail"])
+    ctx.get_timing()
+    step()
+    torch.cuda.synchronize()
+    phases = ctx.get_timing()
+    ctx.set_timing([])
 
     flops = 2.0 * n ** 3
     tflops = flops / (ms_step * 1e-3) / 1e12
@@ -200,7 +210,8 @@ def bench_plain(args):
                      "frac": round(achieved / PEAK_FP64, 4), "traffic": traffic,
                      "avg_launch_ms": round(avg_ms, 4), "launches": s_cnt,
                      "flops_per_launch": schur_flops},
-        "phase_ms_per_step": {ph: round(timing[ph][0] / args.steps, 4) for ph in ("schur", "band", "pivot", "row")},
+        "phase_ms_one_step_untimed": {ph: round(phases[ph][0], 4) for ph in ("schur", "band", "pivot", "row", "tail")},
+        "lookahead_reserved_cus": ctx.lookahead_cus(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -309,13 +309,16 @@ binv_status binv_server_destroy(binv_server* server);
 /* Per-phase kernel timing, for measurement.  Phases: */
 #define BINV_PHASE_PIVOT 0   /* pivot-block inversion (leaf kernels, sub-sweeps) */
 #define BINV_PHASE_ROW 1     /* row panel GEMM */
-#define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM (all tiles, or all
-                                but the next block's band under lookahead) */
+#define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM (all tiles; under
+                                lookahead all but the next block's diagonal
+                                block, on the CU-masked stream) */
 #define BINV_PHASE_OTHER 3   /* copies and panel saves */
 #define BINV_PHASE_BAND 4    /* lookahead: Schur update of the next block's
-                                row and column band, on the side stream */
+                                diagonal block, before the fork */
 #define BINV_PHASE_SMALL 5   /* batched: register-resident tiers (orders <= 128) */
-#define BINV_NPHASE 6
+#define BINV_PHASE_TAIL 6    /* lookahead: the part of the trailing update that
+                                follows the pivot chain on the side stream */
+#define BINV_NPHASE 7
 
 typedef struct {
   double ms[BINV_NPHASE];        /* summed device time of the timed launches */
@@ -323,6 +326,15 @@ typedef struct {
   double flops[BINV_NPHASE];     /* summed algorithmic flops of those launches
                                     (2 K per output element contracted) */
 } binv_timing;
+
+/* CUs reserved for the lookahead's pivot chain (creating the two CU-masked
+ * streams of the lookahead schedule if no call has yet): nres / 8 on each of
+ * the 8 XCDs (nres = 8 unless BINV_SIDE_NCU says otherwise), the trailing
+ * update keeping the rest.  0 means the device refused the CU masks and the
+ * two streams share every CU (the result is the same; the pivot chain then
+ * waits for the trailing update's workgroups).  Errors: BINV_E_INVALID,
+ * BINV_E_HIP. */
+binv_status binv_lookahead_cus(binv_ctx* ctx, int32_t* reserved);
 
 /* Record a pair of hipEvents around every later launch of the phases whose
  * bit (1 << BINV_PHASE_*) is set in `phase_mask` (0 turns timing off), on the

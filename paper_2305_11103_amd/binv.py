@@ -27,7 +27,7 @@ BINV_F_SYNC = 1
 BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
-EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing",
+EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
            "binv_invert_mixed", "binv_residual",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
@@ -40,7 +40,7 @@ BINV_F_SAMPLED_CHECK = 16
 BINV_RESID_ESTIMATE = 1
 BINV_SERVER_STRICT_PRECISION = 1
 BINV_SERVER_FULL_CHECK = 2
-PHASES = ("pivot", "row", "schur", "other", "band", "small")
+PHASES = ("pivot", "row", "schur", "other", "band", "small", "tail")
 TIER_SHAPES = (4, 4, 4, 4, 3)  # launch shapes per register tier (autotuned)
 
 
@@ -55,7 +55,7 @@ class SingularError(BinvError):
 
 
 class _Timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6), ("flops", ctypes.c_double * 6)]
+    _fields_ = [("ms", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7), ("flops", ctypes.c_double * 7)]
 
 
 class _Info(ctypes.Structure):
@@ -104,6 +104,8 @@ def load_library():
     lib.binv_set_timing.restype = ctypes.c_int
     lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
     lib.binv_get_timing.restype = ctypes.c_int
+    lib.binv_lookahead_cus.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.binv_lookahead_cus.restype = ctypes.c_int
     lib.binv_invert_mixed.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts),
                                       ctypes.c_double, ctypes.c_int32, P, ctypes.POINTER(_Info)]
     lib.binv_invert_mixed.restype = ctypes.c_int
@@ -189,6 +191,12 @@ class Context:
         for p in phases:
             mask |= 1 << PHASES.index(p)
         _check(load_library().binv_set_timing(self._h, mask))
+
+    def lookahead_cus(self) -> int:
+        """CUs reserved for the lookahead's pivot chain (0: masks refused)."""
+        r = ctypes.c_int32()
+        _check(load_library().binv_lookahead_cus(self._h, ctypes.byref(r)))
+        return r.value
 
     def get_timing(self) -> dict:
         """Wait for the recorded events; return {phase: (total_ms, launches, flops)}."""

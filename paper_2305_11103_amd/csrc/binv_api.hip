@@ -65,6 +65,47 @@ int sub_block() {
   return v;
 }
 
+// The sweep of a pivot block P (n x n, ld n, n < 2048) with 64-wide
+// sub-blocks, two launches per step: the fused Schur update of step p, which
+// also inverts block p+1's leaf and saves its column panel, then block p+1's
+// row panel.  The same arithmetic as sweep(); 2 k + 2 launches instead of 4 k.
+binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, double* P, const std::vector<int32_t>& part,
+                               hipStream_t s, long long* info, int64_t row0) {
+  const int k = (int)part.size();
+  Level& L = c->lv[level];
+  binv_status st;
+  for (int h = 0; h < 2; ++h) {
+    if ((st = L.ct[h].ensure(sizeof(double) * 64 * (size_t)n)) != BINV_OK) return st;
+    if ((st = L.r[h].ensure(sizeof(double) * 64 * (size_t)n)) != BINV_OK) return st;
+    if ((st = L.p[h].ensure(sizeof(double) * 64 * 64)) != BINV_OK) return st;
+  }
+  std::vector<int64_t> off(k + 1, 0);
+  for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
+  HIP_TRY(binv::launch_leaf_inverse(P, n, (double*)L.p[0].p, part[0], part[0], row0, info, s));
+  HIP_TRY(binv::launch_col_save(P, n, n, 0, part[0], (double*)L.ct[0].p, n, s));
+  HIP_TRY(binv::launch_row_panel((double*)L.p[0].p, part[0], P, n, n, 0, part[0], (double*)L.r[0].p, n, s, nullptr));
+  for (int p = 0; p < k; ++p) {
+    const int cur = p & 1;
+    const double* Ct = (const double*)L.ct[cur].p;
+    const double* R = (const double*)L.r[cur].p;
+    if (p + 1 == k) {
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, P, n, n, off[p], part[p], 0, 0, 0, s, nullptr));
+      break;
+    }
+    binv::SchurLeafArgs a;
+    a.ct_next = (double*)L.ct[cur ^ 1].p;
+    a.ldc_next = n;
+    a.qo = off[p + 1];
+    a.qb = part[p + 1];
+    a.p_next = (double*)L.p[cur ^ 1].p;
+    a.row0 = row0 + off[p + 1];
+    a.info = info;
+    HIP_TRY(binv::launch_schur_leaf(Ct, n, R, n, P, n, n, off[p], part[p], a, s));
+    HIP_TRY(binv::launch_row_panel(a.p_next, a.qb, P, n, n, a.qo, a.qb, (double*)L.r[cur ^ 1].p, n, s, nullptr));
+  }
+  return BINV_OK;
+}
+
 binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw, int b, double* P, hipStream_t s,
                          long long* info, int64_t row0) {
   if (b <= binv::kLeafMax) {
@@ -76,6 +117,7 @@ binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw,
   HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
   std::vector<int32_t> sub;
   for (int off = 0; off < b; off += sub_block()) sub.push_back(std::min(sub_block(), b - off));
+  if (sub_block() == 64 && b < 2048) return nested_sweep_fused(c, level + 1, b, P, sub, s, info, row0);
   return sweep(c, level + 1, b, P, b, sub, s, info, row0, false);
 }
 
@@ -87,10 +129,12 @@ binv_status block_pivot(binv_ctx* c, int level, double* W, int64_t ldw, int64_t 
 }
 
 // Column-panel save and row panel of block [o, o+b) into panel set `buf`.
+// save_cols = false: the column panel was already saved by the Schur update
+// that produced it.
 binv_status block_panels(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, int64_t o, int b, int buf,
-                         hipStream_t s) {
+                         hipStream_t s, bool save_cols = true) {
   Level& L = c->lv[level];
-  {
+  if (save_cols) {
     PhaseTimer t(c, level, BINV_PHASE_OTHER, s);
     HIP_TRY(binv::launch_col_save(W, ldw, n, o, b, (double*)L.ct[buf].p, n, s));
   }
@@ -104,44 +148,50 @@ binv_status block_panels(binv_ctx* c, int level, int64_t n, double* W, int64_t l
 // CUs given to the pivot sub-sweep while the trailing update runs.
 constexpr int kReserveCUs = 8;
 
+// Fraction of every XCD's share of the trailing-update tiles launched on the
+// CU-masked stream (BINV_REST_SPLIT in (0, 1] overrides it).
+constexpr double kRestSplit = 0.75;
+double rest_split() {
+  static const double v = [] {
+    const char* e = getenv("BINV_REST_SPLIT");
+    const double x = e ? atof(e) : kRestSplit;
+    return (x > 0.0 && x <= 1.0) ? x : kRestSplit;
+  }();
+  return v;
+}
+
 binv_status ensure_side(binv_ctx* c) {
   if (c->side) return BINV_OK;
   const int words = (c->ncu + 31) / 32;
-  std::vector<uint32_t> mg(words, 0u), ms(words, 0u);
-  // Workgroups are dealt to the 8 XCDs round-robin whatever the mask, so the
-  // reserved CUs must be spread evenly over the XCDs, or the XCD that lost
-  // them becomes the straggler of every trailing update.  The mask's bits run
-  // XCD by XCD (measured: reserving the last bit of each eighth of the mask
-  // keeps the trailing update at 47.8 TFLOP/s, reserving the last 8 bits drops
-  // it to 42.6), so the reserved CUs are the last ones of each eighth.
-  // BINV_SIDE_NCU overrides how many CUs are reserved (a multiple of 8).
+  std::vector<uint32_t> mg(words, 0u);
+  // The driver deals a stream's CU-mask bits to the 8 XCDs in turn (bit i
+  // goes to XCD i mod 8; measured: a mask whose bits all share one residue
+  // mod 8 is refused, as it leaves the other XCDs without a CU for the
+  // queue).  Workgroups are dealt to the XCDs round-robin too, so every XCD
+  // must keep the same share of the trailing update's CUs: leaving the last
+  // nres bits out of its mask reserves nres / 8 CUs on each XCD.  BINV_SIDE_NCU overrides nres (a
+  // multiple of 8).
   static const int nres = [] {
     const char* e = getenv("BINV_SIDE_NCU");
     const int v = e ? atoi(e) : kReserveCUs;
     return (v >= 8 && v <= 64) ? v / 8 * 8 : kReserveCUs;
   }();
-  std::vector<char> reserved(c->ncu, 0);
-  const int span = std::max(1, c->ncu / 8);
-  for (int x = 0; x < 8; ++x)
-    for (int r = 0; r < nres / 8; ++r) {
-      const int cu = (x + 1) * span - 1 - r;
-      if (cu >= 0 && cu < c->ncu) reserved[cu] = 1;
-    }
-  for (int cu = 0; cu < c->ncu; ++cu) {
-    if (!reserved[cu]) mg[cu / 32] |= 1u << (cu % 32);
-    else ms[cu / 32] |= 1u << (cu % 32);
-  }
-  // CU-masked streams; plain streams if masking is unavailable
-  if (c->ncu <= 2 * nres ||
-      hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) != hipSuccess ||
-      hipExtStreamCreateWithCUMask(&c->side, (uint32_t)words, ms.data()) != hipSuccess) {
+  for (int cu = 0; cu < c->ncu - nres; ++cu) mg[cu / 32] |= 1u << (cu % 32);
+  // The trailing update's stream is CU-masked; the side stream is not: at the
+  // fork the reserved CUs are the only free ones, so the pivot chain runs
+  // there, and the rest of the trailing update that follows it on the side
+  // stream then takes any CU as the first part drains.  Plain streams if the
+  // device refuses the mask (binv_lookahead_cus then reports 0).
+  c->side_cus = 0;
+  if (c->ncu > 2 * nres && hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) == hipSuccess) {
+    c->side_cus = nres;
+  } else {
     if (c->gemm) (void)hipStreamDestroy(c->gemm);
-    if (c->side) (void)hipStreamDestroy(c->side);
-    c->gemm = c->side = nullptr;
+    c->gemm = nullptr;
     (void)hipGetLastError();
     HIP_TRY(hipStreamCreateWithFlags(&c->gemm, hipStreamNonBlocking));
-    HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   }
+  HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_gemm, hipEventDisableTiming));
@@ -177,10 +227,15 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
   }
 
   // Lookahead.  Step p: update block q = p+1's diagonal block first (whole
-  // device), then invert q's pivot block on the side stream (a few reserved
-  // CUs) while the rest of step p's trailing update runs on the other CUs;
-  // join, and form q's column and row panels.  The pivot chain is thus off the
-  // critical path whenever it is shorter than the trailing update.
+  // device), then invert q's pivot block on the side stream while step p's
+  // trailing update runs on the CU-masked stream; the pivot chain starts on
+  // the CUs that mask leaves free, so it is off the critical path whenever it
+  // is shorter than the trailing update.  The last (1 - split) of every XCD's
+  // share of the trailing-update tiles follows the pivot chain on the side
+  // stream, where it can use every CU, so the reserved CUs do not idle once
+  // the chain is done and the masked launch's last round is not left to few
+  // CUs.  Join, and form q's column and row panels.
+  const double split = c->side_cus > 0 ? rest_split() : 1.0;
   if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) return st;
   if ((st = block_panels(c, level, n, W, ldw, off[0], part[0], 0, s)) != BINV_OK) return st;
   for (int p = 0; p < k; ++p) {
@@ -188,27 +243,38 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
     const double* Ct = (const double*)L.ct[cur].p;
     const double* R = (const double*)L.r[cur].p;
     if (p + 1 < k) {
+      // block q's column panel is saved by the launches that update it
+      const binv::ColSave cs{(double*)L.ct[cur ^ 1].p, n, off[p + 1], part[p + 1]};
       {
         // only block q's diagonal block must be current before its pivot
         // inversion starts; its row and column bands join the rest
         PhaseTimer t(c, level, BINV_PHASE_BAND, s);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 3, off[p + 1], part[p + 1], s, t.fl(), 0));
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 3, off[p + 1], part[p + 1], s, t.fl(), 0,
+                                   1.0, &cs));
       }
       HIP_TRY(hipEventRecord(c->ev_fork, s));
       HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
       HIP_TRY(hipStreamWaitEvent(c->gemm, c->ev_fork, 0));
-      if ((st = block_pivot(c, level, W, ldw, off[p + 1], part[p + 1], cur ^ 1, c->side, info, row0)) != BINV_OK)
-        return st;
-      HIP_TRY(hipEventRecord(c->ev_join, c->side));
+      // the trailing update is enqueued first: enqueuing the pivot chain's
+      // launches takes the host a few hundred microseconds, which the
+      // trailing update would otherwise wait out
       {
         PhaseTimer t(c, level, BINV_PHASE_SCHUR, c->gemm);
         HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->gemm,
-                                   t.fl(), 0));
+                                   t.fl(), split < 1.0 ? 1 : 0, split, &cs));
       }
       HIP_TRY(hipEventRecord(c->ev_gemm, c->gemm));
+      if ((st = block_pivot(c, level, W, ldw, off[p + 1], part[p + 1], cur ^ 1, c->side, info, row0)) != BINV_OK)
+        return st;
+      if (split < 1.0) {
+        PhaseTimer t(c, level, BINV_PHASE_TAIL, c->side);
+        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->side,
+                                   t.fl(), 2, split, &cs));
+      }
+      HIP_TRY(hipEventRecord(c->ev_join, c->side));
       HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));
       HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
-      if ((st = block_panels(c, level, n, W, ldw, off[p + 1], part[p + 1], cur ^ 1, s)) != BINV_OK) return st;
+      if ((st = block_panels(c, level, n, W, ldw, off[p + 1], part[p + 1], cur ^ 1, s, false)) != BINV_OK) return st;
     } else {
       PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
       HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, s, t.fl(), 0));
@@ -273,6 +339,17 @@ binv_status binv_destroy(binv_ctx* ctx) {
   (void)hipSetDevice(prev);
   delete ctx;
   return BINV_OK;
+}
+
+binv_status binv_lookahead_cus(binv_ctx* ctx, int32_t* reserved) {
+  if (!ctx || !reserved) return fail(BINV_E_INVALID, "NULL argument");
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  const binv_status st = ensure_side(ctx);
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  *reserved = ctx->side_cus;
+  return st;
 }
 
 binv_status binv_set_timing(binv_ctx* ctx, uint32_t phase_mask) {

@@ -36,6 +36,30 @@ struct StepArgs {
   int region;
   int64_t tr0, tr1, tc0, tc1;
   int64_t ntiles;     // tiles enumerated by the region (before band skipping)
+  // window of each XCD's tile range this launch covers: positions [w0, w1)
+  // of the T8 = ceil(ntiles / 8) positions (w1 = 0: all of them)
+  int64_t w0, w1;
+};
+
+// Column save fused into a Schur update: the elements of columns
+// [c0, c0 + cb) are also stored transposed into p (p[(j - c0) ld + i]), the
+// next block's saved column panel (p == nullptr: none).
+struct ColSave {
+  double* p;
+  int64_t ld;
+  int64_t c0;
+  int cb;
+};
+
+// The next block of a fused nested sweep step (see launch_schur_leaf).
+struct SchurLeafArgs {
+  double* ct_next;    // q's saved column panel (qb x n, k-major)
+  int64_t ldc_next;
+  int64_t qo;         // q's first row/column (a multiple of 64)
+  int qb;             // q's order (<= 64)
+  double* p_next;     // q's leaf inverse (qb x qb, ld qb)
+  int64_t row0;       // global row of W's first row (singular-row report)
+  long long* info;
 };
 
 // One small matrix of a batch.
@@ -80,7 +104,10 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
                             double* R, int64_t ldr, hipStream_t s, double* flops);
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
-                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots);
+                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops,
+                        int part = 0, double split = 1.0, const ColSave* cs = nullptr);
+hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw,
+                             int64_t n, int64_t o, int b, const SchurLeafArgs& a, hipStream_t s);
 hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s);
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
@@ -175,6 +202,7 @@ struct binv_ctx {
   // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few
   // CUs) while the next pivot inversion runs on `side` (masked to the rest)
   hipStream_t side = nullptr, gemm = nullptr;
+  int side_cus = 0;  // CUs reserved for `side`; 0 if the device refused the masks
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
   // autotuned launch shape of each small batched tier, by log2 of the
   // tier's matrix count (-1: not tuned yet)

@@ -317,9 +317,11 @@ typedef double dbl;
 // Inside the range tiles go in groups of GM tile-rows (column-major inside a
 // group), so the workgroups resident on one XCD share row and column panels in
 // that XCD's L2.  Region 1 enumerates only the band of tile-rows [tr0, tr1]
-// and tile-columns [tc0, tc1]; region 2 skips that band.
+// and tile-columns [tc0, tc1]; region 2 skips that band.  A launch may cover
+// a window [w0, w1) of positions inside every XCD's range (the trailing update
+// split in two launches keeps each part spread over all XCDs).
 template <int GM>
-__device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64_t& tm, int64_t& tn, int region,
+__host__ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t TN, int64_t& tm, int64_t& tn, int region,
                                         int64_t tr0, int64_t tr1, int64_t tc0, int64_t tc1) {
   if (region == 1) {
     const int64_t nr = tr1 - tr0 + 1, nc = tc1 - tc0 + 1;
@@ -374,9 +376,13 @@ struct TileCfg {
 };
 
 // One output tile (tm, tn) of a step GEMM.
-template <int MODE, class C, bool A_KMAJOR, bool VEC>
+// With CS (Schur update only), elements of columns [cs0, cs0 + csb) are also
+// stored transposed into cs (cs[(j - cs0) ldcs + i]): the next block's saved
+// column panel, written as its values are produced.
+template <int MODE, class C, bool A_KMAJOR, bool VEC, bool CS = false>
 __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t tn,
-                                          double (&As)[2][C::BK * C::LA], double (&Bs)[2][C::BK * C::LB]) {
+                                          double (&As)[2][C::BK * C::LA], double (&Bs)[2][C::BK * C::LB],
+                                          double* cs = nullptr, int64_t ldcs = 0, int64_t cs0 = 0, int csb = 0) {
   constexpr int BM = C::BM, BN = C::BN, NWM = C::NWM, NWN = C::NWN, NT = C::NT, BK = C::BK;
   constexpr int LA = C::LA, LB = C::LB;
   constexpr int WM = BM / NWM, WN = BN / NWN;
@@ -548,30 +554,62 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
         g.W[i * g.ldw + j] = jp ? g.R[i * g.ldr + (j - o)] : acc[r][c];
       } else {
         const bool ip = (i >= o && i < o + b);
-        double* dst = &g.W[i * g.ldw + j];
+        double val;
         if (ip) {
-          *dst = g.R[(i - o) * g.ldr + j];
+          val = g.R[(i - o) * g.ldr + j];
         } else {
           const double w = jp ? 0.0 : g.Win[i * g.ldwin + j];
-          *dst = w - acc[r][c];
+          val = w - acc[r][c];
         }
+        g.W[i * g.ldw + j] = val;
+        if (CS && j >= cs0 && j < cs0 + csb) cs[(j - cs0) * ldcs + i] = val;
       }
     }
   }
 }
 
-template <int MODE, class C, bool A_KMAJOR, bool VEC>
+template <int MODE, class C, bool A_KMAJOR, bool VEC, bool CS>
 __global__ void __launch_bounds__(C::NT)
-__attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g) {
+__attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g, ColSave cs) {
   __shared__ double As[2][C::BK * C::LA];
   __shared__ double Bs[2][C::BK * C::LB];
   const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
   const int64_t T8 = (g.ntiles + 7) / 8;
+  const int64_t w0 = g.w1 ? g.w0 : 0, w1 = g.w1 ? g.w1 : T8;
   const int64_t xcd = blockIdx.x & 7, per = (int64_t)gridDim.x >> 3;
-  for (int64_t tl = (int64_t)blockIdx.x >> 3; tl < T8; tl += per) {
+  for (int64_t tl = w0 + ((int64_t)blockIdx.x >> 3); tl < w1; tl += per) {
     int64_t tm, tn;
     if (!tile_of<8>(xcd * T8 + tl, TM, TN, tm, tn, g.region, g.tr0, g.tr1, g.tc0, g.tc1)) continue;
-    gemm_tile<MODE, C, A_KMAJOR, VEC>(g, tm, tn, As, Bs);
+    gemm_tile<MODE, C, A_KMAJOR, VEC, CS>(g, tm, tn, As, Bs, cs.p, cs.ld, cs.c0, cs.cb);
+  }
+}
+
+// One step of a pivot block's nested sweep with 64-wide sub-blocks, fused:
+// the Schur update of step p on 64 x 64 tiles, where workgroup 0 updates the
+// next block q's diagonal tile first and then inverts it (the leaf of step q)
+// while the other workgroups update the remaining tiles, and every tile of
+// block q's columns also stores its values into q's saved column panel.  The
+// arithmetic is that of the separate Schur, leaf and column-save launches, in
+// one launch instead of three, with the leaf overlapping the update.
+template <bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_schur_leaf(StepArgs g, SchurLeafArgs a) {
+  using C = TileCfg<64, 64, 2, 2>;
+  static_assert(C::NT == 256, "the leaf runs on the tile's 4 waves");
+  __shared__ double As[2][C::BK * C::LA];
+  __shared__ double Bs[2][C::BK * C::LB];
+  const int64_t TM = (g.M + C::BM - 1) / C::BM, TN = (g.N + C::BN - 1) / C::BN;
+  const int64_t tq = a.qo / C::BM;
+  if (blockIdx.x == 0) {
+    gemm_tile<MODE_SCHUR, C, true, VEC, true>(g, tq, tq, As, Bs, a.ct_next, a.ldc_next, a.qo, a.qb);
+    __syncthreads();  // the tile's stores are visible to the whole workgroup
+    leaf_body<1, 16, 4>(g.W + a.qo * g.ldw + a.qo, g.ldw, a.p_next, a.qb, a.qb, a.row0, a.info);
+    return;
+  }
+  const int64_t skip = tq * TN + tq;
+  for (int64_t t = (int64_t)blockIdx.x - 1; t < TM * TN - 1; t += (int64_t)gridDim.x - 1) {
+    const int64_t u = t >= skip ? t + 1 : t;
+    gemm_tile<MODE_SCHUR, C, true, VEC, true>(g, u / TN, u % TN, As, Bs, a.ct_next, a.ldc_next, a.qo, a.qb);
   }
 }
 
@@ -624,42 +662,42 @@ hipError_t launch_zero_info(long long* p, hipStream_t s) {
 
 // Algorithmic flops of one step launch: 2 K per output element that needs the
 // contraction (rows of block p are copies in the Schur update, columns of
-// block p copies in the row panel).
+// block p copies in the row panel), over the tiles the launch covers (the
+// region, and the window of every XCD's range when g.w1 > 0).
 template <int BM, int BN>
 static double step_flops(const StepArgs& g, int mode) {
   const int64_t TM = (g.M + BM - 1) / BM, TN = (g.N + BN - 1) / BN;
-  auto inband = [&](int64_t tm, int64_t tn) {
-    return (tm >= g.tr0 && tm <= g.tr1) || (tn >= g.tc0 && tn <= g.tc1);
-  };
-  double cnt = 0;
-  for (int64_t tm = 0; tm < TM; ++tm) {
+  auto tile_elems = [&](int64_t tm, int64_t tn) {
     const int64_t r0 = tm * BM, r1 = (r0 + BM < g.M) ? r0 + BM : g.M;
     int64_t rows = r1 - r0;
     if (mode == MODE_SCHUR) {
       const int64_t a = (r0 > g.o) ? r0 : g.o, z = (r1 < g.o + g.b) ? r1 : g.o + g.b;
       if (z > a) rows -= z - a;
     }
-    for (int64_t tn = 0; tn < TN; ++tn) {
-      const bool indiag = tm >= g.tr0 && tm <= g.tr1 && tn >= g.tc0 && tn <= g.tc1;
-      if (g.region == 1 && !inband(tm, tn)) continue;
-      if (g.region == 2 && inband(tm, tn)) continue;
-      if (g.region == 3 && !indiag) continue;
-      if (g.region == 4 && indiag) continue;
-      const int64_t c0 = tn * BN, c1 = (c0 + BN < g.N) ? c0 + BN : g.N;
-      int64_t cols = c1 - c0;
-      if (mode == MODE_ROW) {
-        const int64_t a = (c0 > g.o) ? c0 : g.o, z = (c1 < g.o + g.b) ? c1 : g.o + g.b;
-        if (z > a) cols -= z - a;
-      }
-      cnt += (double)rows * (double)cols;
+    const int64_t c0 = tn * BN, c1 = (c0 + BN < g.N) ? c0 + BN : g.N;
+    int64_t cols = c1 - c0;
+    if (mode == MODE_ROW) {
+      const int64_t a = (c0 > g.o) ? c0 : g.o, z = (c1 < g.o + g.b) ? c1 : g.o + g.b;
+      if (z > a) cols -= z - a;
     }
-  }
+    return (double)rows * (double)cols;
+  };
+  double cnt = 0;
+  const int64_t T8 = (g.ntiles + 7) / 8;
+  const int64_t w0 = g.w1 ? g.w0 : 0, w1 = g.w1 ? g.w1 : T8;
+  for (int64_t x = 0; x < 8; ++x)
+    for (int64_t tl = w0; tl < w1; ++tl) {
+      int64_t tm, tn;
+      if (tile_of<8>(x * T8 + tl, TM, TN, tm, tn, g.region, g.tr0, g.tr1, g.tc0, g.tc1)) cnt += tile_elems(tm, tn);
+    }
   return 2.0 * g.K * cnt;
 }
 
+// part 0: every tile of the region; part 1 / part 2: the first `split` / the
+// remaining 1 - `split` of the positions of every XCD's tile range.
 template <int MODE, int BM, int BN, bool AK, int NWM = 2, int NWN = 2>
 static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo, int qb, double* flops,
-                              int slots = 0) {
+                              int slots = 0, int part = 0, double split = 1.0, const ColSave* cs = nullptr) {
   using C = TileCfg<BM, BN, NWM, NWN>;
   constexpr int BK = C::BK;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
@@ -675,17 +713,41 @@ static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo,
     if (region == 1) T = (g.tr1 - g.tr0 + 1) * TN + (TM - (g.tr1 - g.tr0 + 1)) * (g.tc1 - g.tc0 + 1);
     if (region == 3) T = (g.tr1 - g.tr0 + 1) * (g.tc1 - g.tc0 + 1);
   }
-  if (flops) *flops = step_flops<BM, BN>(g, MODE);
   g.ntiles = T;
-  int64_t G = (T + 7) / 8 * 8;  // multiple of 8 for the XCD-aware tile order
+  const int64_t T8 = (T + 7) / 8;
+  g.w0 = 0;
+  g.w1 = 0;
+  if (part != 0) {
+    int64_t w = (int64_t)(split * (double)T8 + 0.5);
+    w = w < 0 ? 0 : (w > T8 ? T8 : w);
+    g.w0 = part == 1 ? 0 : w;
+    g.w1 = part == 1 ? w : T8;
+    if (g.w1 <= g.w0) {
+      if (flops) *flops = 0.0;
+      return hipSuccess;  // an empty part
+    }
+  }
+  if (flops) *flops = step_flops<BM, BN>(g, MODE);
+  int64_t G = 8 * (g.w1 ? g.w1 - g.w0 : T8);  // multiple of 8 for the XCD-aware tile order
   if (slots > 0 && G > slots) G = (int64_t)slots / 8 * 8;
   if (G < 8) G = 8;
   const bool vec = (g.M % BM == 0) && (g.N % BN == 0) && (g.K % BK == 0) && ((g.lda & 1) == 0) &&
                    ((g.ldb & 1) == 0) && ((((uintptr_t)g.A) & 15) == 0) && ((((uintptr_t)g.B) & 15) == 0);
-  if (vec)
-    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, true>), dim3((unsigned)G), dim3(C::NT), 0, s, g);
-  else
-    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, false>), dim3((unsigned)G), dim3(C::NT), 0, s, g);
+  const ColSave none{nullptr, 0, 0, 0};
+  if constexpr (MODE == MODE_SCHUR) {
+    if (cs && cs->p) {
+      if (vec)
+        hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, true, true>), dim3((unsigned)G), dim3(C::NT), 0, s, g, *cs);
+      else
+        hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, false, true>), dim3((unsigned)G), dim3(C::NT), 0, s, g, *cs);
+      return hipGetLastError();
+    }
+  }
+  if (vec) {
+    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, true, false>), dim3((unsigned)G), dim3(C::NT), 0, s, g, none);
+  } else {
+    hipLaunchKernelGGL((k_gemm_step<MODE, C, AK, false, false>), dim3((unsigned)G), dim3(C::NT), 0, s, g, none);
+  }
   return hipGetLastError();
 }
 
@@ -706,11 +768,14 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 // k-major) and the row panel R (b x n).  region 0: all tiles; 1: only the
 // tile band covering rows/columns [qo, qo+qb) of the next block; 2: the rest;
 // 3: only the tiles of the next block's diagonal block (rows and columns
-// [qo, qo+qb)); 4: every tile but those.
+// [qo, qo+qb)); 4: every tile but those.  part 1 / 2 with `split`: the first
+// `split` / the rest of every XCD's share of the region's tiles.  cs: the
+// next block's column panel saved as its elements are updated.
 int schur_tile(int64_t n) { return n >= 2048 ? 128 : 64; }
 
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
-                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int slots) {
+                        int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops, int part,
+                        double split, const ColSave* cs) {
   StepArgs g;
   g.A = Ct; g.lda = ldc;
   g.B = R; g.ldb = ldr;
@@ -725,10 +790,37 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
     const int64_t tile = schur_tile(n);
     const int64_t a0 = qo / tile * tile;
     const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
-    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0);
+    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 0, 1.0, cs);
   }
-  if (schur_tile(n) == 128) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, slots);
-  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, slots);
+  if (schur_tile(n) == 128)
+    return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, 0, part, split, cs);
+  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, 0, part, split, cs);
+}
+
+// The fused nested step: Schur update of step p (block [o, o+b)) in place on
+// W (n x n, n < 2048), with the leaf of block q = [qo, qo+qb) (qo a multiple
+// of 64, qb <= 64) into p_next (ld qb) and q's column panel into ct_next.
+hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw,
+                             int64_t n, int64_t o, int b, const SchurLeafArgs& a, hipStream_t s) {
+  if (n <= 0 || n >= 2048 || a.qo % 64 != 0 || a.qb <= 0 || a.qb > 64 || a.qo + a.qb > n || b <= 0)
+    return hipErrorInvalidValue;
+  StepArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = Ct; g.lda = ldc;
+  g.B = R; g.ldb = ldr;
+  g.W = W; g.ldw = ldw;
+  g.Win = W; g.ldwin = ldw;
+  g.R = R; g.ldr = ldr;
+  g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
+  const int64_t TT = (n + 63) / 64;
+  const unsigned G = (unsigned)(TT * TT);  // one workgroup per tile
+  const bool vec = (n % 64 == 0) && (b % 16 == 0) && ((ldc & 1) == 0) && ((ldr & 1) == 0) &&
+                   ((((uintptr_t)Ct) & 15) == 0) && ((((uintptr_t)R) & 15) == 0);
+  if (vec)
+    hipLaunchKernelGGL(k_schur_leaf<true>, dim3(G), dim3(256), 0, s, g, a);
+  else
+    hipLaunchKernelGGL(k_schur_leaf<false>, dim3(G), dim3(256), 0, s, g, a);
+  return hipGetLastError();
 }
 
 // Plain FP64 products for the refinement: C = I - A B (resid) or C = Cin + A B,

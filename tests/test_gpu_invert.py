@@ -161,21 +161,32 @@ def test_lookahead_is_bitwise_identical(gpu, n, part):
     _check(A, X1)
 
 
+def test_lookahead_reserves_cus_on_every_xcd(gpu):
+    """The pivot chain's stream is CU-masked to one CU per XCD (8 of the
+    device's CUs), the trailing update's stream to the rest: the device must
+    accept both masks, or the lookahead would fall back to unmasked streams."""
+    import torch
+    from paper_2305_11103_amd import binv
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert binv.Context(0).lookahead_cus() == (8 if ncu > 16 else 0)
+
+
 def test_timing_reports_flops(gpu):
     import torch
     from paper_2305_11103_amd import binv
     n, blk = 2048, 512
     A = torch.from_numpy(wl.diag_dominant(n, 3)).cuda()
     ctx = binv.default_context(0)
-    ctx.set_timing(["schur", "band", "row", "pivot"])
+    ctx.set_timing(["schur", "band", "tail", "row", "pivot"])
     ctx.get_timing()
     binv.invert(A, block=blk, ctx=ctx)
     t = ctx.get_timing()
     ctx.set_timing([])
     # every contracted element of the trailing update costs 2 b flops: the
-    # trailing update plus lookahead band cover 2 b (n - b) n per block
+    # trailing update, the lookahead's diagonal-block update and the part that
+    # follows the pivot chain cover 2 b (n - b) n per block
     k = n // blk
-    assert t["schur"][2] + t["band"][2] == pytest.approx(k * 2.0 * blk * (n - blk) * n)
+    assert t["schur"][2] + t["band"][2] + t["tail"][2] == pytest.approx(k * 2.0 * blk * (n - blk) * n)
     assert t["row"][2] == pytest.approx(k * 2.0 * blk * blk * (n - blk))
     assert t["schur"][1] == k and t["band"][1] == k - 1
 
