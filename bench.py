@@ -449,7 +449,11 @@ def bench_serve(args):
     sizes, conds, tags = workloads.request_stream(N, workloads.stream_seed(5, 0))
     seeds = [workloads.stream_seed(5, 1 + i) for i in range(N)]
     flops = float(np.sum(2.0 * sizes.astype(np.float64) ** 3))
-    ctx = binv.default_context(0)
+    # the serial baselines get a context of their own, closed before the
+    # server starts: a context that has run the lookahead holds a CU-masked
+    # stream, i.e. a hardware queue of its own, which the server's streams
+    # would otherwise have to do without
+    ctx = binv.Context(0)
     cur = torch.cuda.current_stream(dev)
     budget = args.budget_gib << 30
 
@@ -505,6 +509,8 @@ def bench_serve(args):
     mu = N / t_checked
     log(f"bench: serial capacity {mu_plain:.1f}/s plain, {mu:.1f}/s checked")
     del X_full
+    torch.cuda.synchronize()
+    ctx.close()
     torch.cuda.empty_cache()
 
     def run(rate, label, strict=False):

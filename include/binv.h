@@ -327,12 +327,15 @@ typedef struct {
                                     (2 K per output element contracted) */
 } binv_timing;
 
-/* CUs reserved for the lookahead's pivot chain (creating the two CU-masked
- * streams of the lookahead schedule if no call has yet): nres / 8 on each of
- * the 8 XCDs (nres = 8 unless BINV_SIDE_NCU says otherwise), the trailing
- * update keeping the rest.  0 means the device refused the CU masks and the
- * two streams share every CU (the result is the same; the pivot chain then
- * waits for the trailing update's workgroups).  Errors: BINV_E_INVALID,
+/* CUs reserved for the lookahead's pivot chain (creating the lookahead's
+ * streams if no call has yet): nres / 8 on each of the 8 XCDs (nres = 8
+ * unless BINV_SIDE_NCU says otherwise; 0 there disables the mask), the
+ * trailing update's stream being CU-masked to the rest.  0 means no mask: the
+ * device refused it or it is disabled, and the pivot chain competes with the
+ * trailing update for every CU (the result is the same).  A CU-masked stream
+ * holds a hardware queue of its own for the context's lifetime; a process that
+ * overlaps work on many streams of its own (as binv_server does) has fewer
+ * queues to share while such a context exists.  Errors: BINV_E_INVALID,
  * BINV_E_HIP. */
 binv_status binv_lookahead_cus(binv_ctx* ctx, int32_t* reserved);
 

@@ -145,19 +145,24 @@ binv_status block_panels(binv_ctx* c, int level, int64_t n, double* W, int64_t l
   return BINV_OK;
 }
 
-// CUs given to the pivot sub-sweep while the trailing update runs.
-constexpr int kReserveCUs = 8;
+// CUs left out of the trailing update's CU mask for the pivot chain: none by
+// default (BINV_SIDE_NCU = 8..64 sets a multiple of 8).  Measured at b = 512:
+// once the trailing update is enqueued ahead of the pivot chain, a mask costs
+// the trailing update more than it gains the chain (n = 8192: 25.6 against
+// 24.3 ms; 16384: 182.6 against 163.0 ms; 4096: 6.84 against 6.96 ms).
+constexpr int kReserveCUs = 0;
 
 // Fraction of every XCD's share of the trailing-update tiles launched on the
-// CU-masked stream (BINV_REST_SPLIT in (0, 1] overrides it).
-constexpr double kRestSplit = 0.75;
-double rest_split() {
+// trailing update's stream; the rest follows the pivot chain on the side
+// stream.  0.75 with a CU mask, 1 (no tail launch) without; BINV_REST_SPLIT in
+// (0, 1] overrides both.
+double rest_split(bool masked) {
   static const double v = [] {
     const char* e = getenv("BINV_REST_SPLIT");
-    const double x = e ? atof(e) : kRestSplit;
-    return (x > 0.0 && x <= 1.0) ? x : kRestSplit;
+    const double x = e ? atof(e) : -1.0;
+    return (x > 0.0 && x <= 1.0) ? x : -1.0;
   }();
-  return v;
+  return v > 0.0 ? v : (masked ? 0.75 : 1.0);
 }
 
 binv_status ensure_side(binv_ctx* c) {
@@ -169,21 +174,22 @@ binv_status ensure_side(binv_ctx* c) {
   // mod 8 is refused, as it leaves the other XCDs without a CU for the
   // queue).  Workgroups are dealt to the XCDs round-robin too, so every XCD
   // must keep the same share of the trailing update's CUs: leaving the last
-  // nres bits out of its mask reserves nres / 8 CUs on each XCD.  BINV_SIDE_NCU overrides nres (a
-  // multiple of 8).
+  // nres bits out of its mask reserves nres / 8 CUs on each XCD.
+  // BINV_SIDE_NCU sets nres (a multiple of 8); by default there is no mask.
   static const int nres = [] {
     const char* e = getenv("BINV_SIDE_NCU");
     const int v = e ? atoi(e) : kReserveCUs;
-    return (v >= 8 && v <= 64) ? v / 8 * 8 : kReserveCUs;
+    return (v >= 8 && v <= 64) ? v / 8 * 8 : 0;  // 0: no mask, every CU for both streams
   }();
   for (int cu = 0; cu < c->ncu - nres; ++cu) mg[cu / 32] |= 1u << (cu % 32);
-  // The trailing update's stream is CU-masked; the side stream is not: at the
-  // fork the reserved CUs are the only free ones, so the pivot chain runs
-  // there, and the rest of the trailing update that follows it on the side
-  // stream then takes any CU as the first part drains.  Plain streams if the
-  // device refuses the mask (binv_lookahead_cus then reports 0).
+  // With a mask, only the trailing update's stream is CU-masked: at the fork
+  // the reserved CUs are the only free ones, so the pivot chain runs there,
+  // and the rest of the trailing update that follows it on the side stream
+  // takes any CU as the first part drains.  Plain streams without a mask or if
+  // the device refuses it (binv_lookahead_cus then reports 0).
   c->side_cus = 0;
-  if (c->ncu > 2 * nres && hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) == hipSuccess) {
+  if (c->cu_mask && nres > 0 && c->ncu > 2 * nres &&
+      hipExtStreamCreateWithCUMask(&c->gemm, (uint32_t)words, mg.data()) == hipSuccess) {
     c->side_cus = nres;
   } else {
     if (c->gemm) (void)hipStreamDestroy(c->gemm);
@@ -226,60 +232,64 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
     return BINV_OK;
   }
 
-  // Lookahead.  Step p: update block q = p+1's diagonal block first (whole
-  // device), then invert q's pivot block on the side stream while step p's
-  // trailing update runs on the CU-masked stream; the pivot chain starts on
-  // the CUs that mask leaves free, so it is off the critical path whenever it
-  // is shorter than the trailing update.  The last (1 - split) of every XCD's
-  // share of the trailing-update tiles follows the pivot chain on the side
-  // stream, where it can use every CU, so the reserved CUs do not idle once
-  // the chain is done and the masked launch's last round is not left to few
-  // CUs.  Join, and form q's column and row panels.
-  const double split = c->side_cus > 0 ? rest_split() : 1.0;
+  // Lookahead.  After block 0's panels every launch on the critical path runs
+  // on the trailing update's stream g, so consecutive steps hand over nothing
+  // but the pivot chain.  Step p: update block q = p+1's diagonal block; fork:
+  // the trailing update on g and q's pivot inversion on the side stream, so
+  // the chain is off the critical path whenever it is shorter than the
+  // trailing update (its workgroups take CUs as the update's drain, or the CUs
+  // a mask on g leaves free).  With split < 1 the last (1 - split) of every
+  // XCD's share of the trailing-update tiles follows the chain on the side
+  // stream, where it can use every CU, so reserved CUs do not idle once the
+  // chain is done.  g waits for the side stream, then forms q's row panel;
+  // q's column panel is saved by the launches that update it.
+  const double split = rest_split(c->side_cus > 0);
   if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) return st;
   if ((st = block_panels(c, level, n, W, ldw, off[0], part[0], 0, s)) != BINV_OK) return st;
+  hipStream_t g = c->gemm;
+  HIP_TRY(hipEventRecord(c->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(g, c->ev_fork, 0));
   for (int p = 0; p < k; ++p) {
     const int cur = p & 1;
     const double* Ct = (const double*)L.ct[cur].p;
     const double* R = (const double*)L.r[cur].p;
-    if (p + 1 < k) {
-      // block q's column panel is saved by the launches that update it
-      const binv::ColSave cs{(double*)L.ct[cur ^ 1].p, n, off[p + 1], part[p + 1]};
-      {
-        // only block q's diagonal block must be current before its pivot
-        // inversion starts; its row and column bands join the rest
-        PhaseTimer t(c, level, BINV_PHASE_BAND, s);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 3, off[p + 1], part[p + 1], s, t.fl(), 0,
-                                   1.0, &cs));
-      }
-      HIP_TRY(hipEventRecord(c->ev_fork, s));
-      HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-      HIP_TRY(hipStreamWaitEvent(c->gemm, c->ev_fork, 0));
-      // the trailing update is enqueued first: enqueuing the pivot chain's
-      // launches takes the host a few hundred microseconds, which the
-      // trailing update would otherwise wait out
-      {
-        PhaseTimer t(c, level, BINV_PHASE_SCHUR, c->gemm);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->gemm,
-                                   t.fl(), split < 1.0 ? 1 : 0, split, &cs));
-      }
-      HIP_TRY(hipEventRecord(c->ev_gemm, c->gemm));
-      if ((st = block_pivot(c, level, W, ldw, off[p + 1], part[p + 1], cur ^ 1, c->side, info, row0)) != BINV_OK)
-        return st;
-      if (split < 1.0) {
-        PhaseTimer t(c, level, BINV_PHASE_TAIL, c->side);
-        HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->side,
-                                   t.fl(), 2, split, &cs));
-      }
-      HIP_TRY(hipEventRecord(c->ev_join, c->side));
-      HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));
-      HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
-      if ((st = block_panels(c, level, n, W, ldw, off[p + 1], part[p + 1], cur ^ 1, s, false)) != BINV_OK) return st;
-    } else {
-      PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
-      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, s, t.fl(), 0));
+    if (p + 1 == k) {
+      PhaseTimer t(c, level, BINV_PHASE_SCHUR, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, g, t.fl(), 0));
+      break;
     }
+    // block q's column panel is saved by the launches that update it
+    const binv::ColSave cs{(double*)L.ct[cur ^ 1].p, n, off[p + 1], part[p + 1]};
+    {
+      // only block q's diagonal block must be current before its pivot
+      // inversion starts; its row and column bands join the rest
+      PhaseTimer t(c, level, BINV_PHASE_BAND, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 3, off[p + 1], part[p + 1], g, t.fl(), 0,
+                                 1.0, &cs));
+    }
+    HIP_TRY(hipEventRecord(c->ev_fork, g));
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    // the trailing update is enqueued first: enqueuing the pivot chain's
+    // launches takes the host a few hundred microseconds, which the trailing
+    // update would otherwise wait out
+    {
+      PhaseTimer t(c, level, BINV_PHASE_SCHUR, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], g, t.fl(),
+                                 split < 1.0 ? 1 : 0, split, &cs));
+    }
+    if ((st = block_pivot(c, level, W, ldw, off[p + 1], part[p + 1], cur ^ 1, c->side, info, row0)) != BINV_OK)
+      return st;
+    if (split < 1.0) {
+      PhaseTimer t(c, level, BINV_PHASE_TAIL, c->side);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 4, off[p + 1], part[p + 1], c->side,
+                                 t.fl(), 2, split, &cs));
+    }
+    HIP_TRY(hipEventRecord(c->ev_join, c->side));
+    HIP_TRY(hipStreamWaitEvent(g, c->ev_join, 0));
+    if ((st = block_panels(c, level, n, W, ldw, off[p + 1], part[p + 1], cur ^ 1, g, false)) != BINV_OK) return st;
   }
+  HIP_TRY(hipEventRecord(c->ev_gemm, g));
+  HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));
   return BINV_OK;
 }
 

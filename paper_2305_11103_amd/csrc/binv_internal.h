@@ -203,6 +203,7 @@ struct binv_ctx {
   // CUs) while the next pivot inversion runs on `side` (masked to the rest)
   hipStream_t side = nullptr, gemm = nullptr;
   int side_cus = 0;  // CUs reserved for `side`; 0 if the device refused the masks
+  bool cu_mask = true;  // false: lookahead on unmasked streams (a server's workers)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
   // autotuned launch shape of each small batched tier, by log2 of the
   // tier's matrix count (-1: not tuned yet)

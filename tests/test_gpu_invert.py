@@ -161,14 +161,45 @@ def test_lookahead_is_bitwise_identical(gpu, n, part):
     _check(A, X1)
 
 
-def test_lookahead_reserves_cus_on_every_xcd(gpu):
-    """The pivot chain's stream is CU-masked to one CU per XCD (8 of the
-    device's CUs), the trailing update's stream to the rest: the device must
-    accept both masks, or the lookahead would fall back to unmasked streams."""
+_MASK_CHECK = """
+import numpy as np, torch
+from paper_2305_11103_amd import binv, workloads as wl
+ctx = binv.Context(0)
+print("reserved", ctx.lookahead_cus())
+A = torch.from_numpy(wl.diag_dominant(1536, 5)).cuda()
+X1 = binv.invert(A, block=256, ctx=ctx, lookahead=True)
+X2 = binv.invert(A, block=256, ctx=ctx, lookahead=False)
+torch.cuda.synchronize()
+print("bitwise", bool(torch.equal(X1, X2)))
+"""
+
+
+@pytest.mark.parametrize("env,reserved", [({"BINV_SIDE_NCU": "8"}, 8), ({"BINV_REST_SPLIT": "0.6"}, 0)])
+def test_lookahead_modes_in_a_fresh_process(gpu, env, reserved):
+    """The lookahead's stream settings are read once per process, so each mode
+    runs in a child process (one at a time): with BINV_SIDE_NCU = 8 the device
+    must accept the trailing update's CU mask (one CU left out per XCD; the
+    mask's bits go to the XCDs in turn), and with or without it, with the
+    trailing update split around the pivot chain, the result must be bitwise
+    equal to the serial schedule."""
+    import os
+    import subprocess
+    import sys
     import torch
-    from paper_2305_11103_amd import binv
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    assert binv.Context(0).lookahead_cus() == (8 if ncu > 16 else 0)
+    e = dict(os.environ, **env)
+    out = subprocess.run([sys.executable, "-c", _MASK_CHECK], cwd=root, env=e, capture_output=True, text=True,
+                         timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    lines = dict(l.split(" ", 1) for l in out.stdout.strip().splitlines() if " " in l)
+    assert int(lines["reserved"]) == (reserved if ncu > 16 else 0)
+    assert lines["bitwise"] == "True"
+
+
+def test_lookahead_has_no_mask_by_default(gpu):
+    from paper_2305_11103_amd import binv
+    assert binv.Context(0).lookahead_cus() == 0
 
 
 def test_timing_reports_flops(gpu):
