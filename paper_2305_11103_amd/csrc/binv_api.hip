@@ -65,13 +65,16 @@ int sub_block() {
   return v;
 }
 
-// The sweep of a pivot block P (n x n, ld n, n < 2048) with 64-wide
-// sub-blocks, two launches per step: the fused Schur update of step p, which
-// also inverts block p+1's leaf and saves its column panel, then block p+1's
-// row panel.  The same arithmetic as sweep(); 2 k + 2 launches instead of 4 k.
-binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, double* P, const std::vector<int32_t>& part,
-                               hipStream_t s, long long* info, int64_t row0) {
+// The sweep of a pivot block (n x n, n < 2048, read from Wpp with leading
+// dimension ldwp) into P (n x n, ld n) with 64-wide sub-blocks, two launches
+// per step: the fused Schur update of step p, which also inverts block p+1's
+// leaf and saves its column panel, then block p+1's row panel.  Step 0 reads
+// the block where it lies and writes every element of P, so no copy is made.
+// The same arithmetic as sweep() on a copy; 2 k + 1 launches instead of 4 k + 1.
+binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, const double* Wpp, int64_t ldwp, double* P,
+                               const std::vector<int32_t>& part, hipStream_t s, long long* info, int64_t row0) {
   const int k = (int)part.size();
+  if (k < 2) return fail(BINV_E_INVALID, "fused nested sweep needs two sub-blocks or more");
   Level& L = c->lv[level];
   binv_status st;
   for (int h = 0; h < 2; ++h) {
@@ -81,9 +84,10 @@ binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, double* P, con
   }
   std::vector<int64_t> off(k + 1, 0);
   for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
-  HIP_TRY(binv::launch_leaf_inverse(P, n, (double*)L.p[0].p, part[0], part[0], row0, info, s));
-  HIP_TRY(binv::launch_col_save(P, n, n, 0, part[0], (double*)L.ct[0].p, n, s));
-  HIP_TRY(binv::launch_row_panel((double*)L.p[0].p, part[0], P, n, n, 0, part[0], (double*)L.r[0].p, n, s, nullptr));
+  HIP_TRY(binv::launch_leaf_inverse(Wpp, ldwp, (double*)L.p[0].p, part[0], part[0], row0, info, s));
+  HIP_TRY(binv::launch_col_save(Wpp, ldwp, n, 0, part[0], (double*)L.ct[0].p, n, s));
+  HIP_TRY(binv::launch_row_panel((double*)L.p[0].p, part[0], Wpp, ldwp, n, 0, part[0], (double*)L.r[0].p, n, s,
+                                 nullptr));
   for (int p = 0; p < k; ++p) {
     const int cur = p & 1;
     const double* Ct = (const double*)L.ct[cur].p;
@@ -100,7 +104,9 @@ binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, double* P, con
     a.p_next = (double*)L.p[cur ^ 1].p;
     a.row0 = row0 + off[p + 1];
     a.info = info;
-    HIP_TRY(binv::launch_schur_leaf(Ct, n, R, n, P, n, n, off[p], part[p], a, s));
+    const double* Win = p == 0 ? Wpp : P;
+    const int64_t ldwin = p == 0 ? ldwp : n;
+    HIP_TRY(binv::launch_schur_leaf(Ct, n, R, n, P, n, Win, ldwin, n, off[p], part[p], a, s));
     HIP_TRY(binv::launch_row_panel(a.p_next, a.qb, P, n, n, a.qo, a.qb, (double*)L.r[cur ^ 1].p, n, s, nullptr));
   }
   return BINV_OK;
@@ -113,11 +119,12 @@ binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw,
     return BINV_OK;
   }
   if (level + 1 >= 2) return fail(BINV_E_INVALID, "pivot block too large for the recursion depth");
-  // invert a copy in place by the same sweep with 64-wide sub-blocks, then use it as P
-  HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
+  // the same sweep with 64-wide sub-blocks, into P
   std::vector<int32_t> sub;
   for (int off = 0; off < b; off += sub_block()) sub.push_back(std::min(sub_block(), b - off));
-  if (sub_block() == 64 && b < 2048) return nested_sweep_fused(c, level + 1, b, P, sub, s, info, row0);
+  if (sub_block() == 64 && b < 2048) return nested_sweep_fused(c, level + 1, b, Wpp, ldw, P, sub, s, info, row0);
+  // generic: invert a copy in place
+  HIP_TRY(binv::launch_copy2d(Wpp, ldw, P, b, b, b, s));
   return sweep(c, level + 1, b, P, b, sub, s, info, row0, false);
 }
 

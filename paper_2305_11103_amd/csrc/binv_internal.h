@@ -107,7 +107,8 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
                         int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops,
                         int part = 0, double split = 1.0, const ColSave* cs = nullptr);
 hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw,
-                             int64_t n, int64_t o, int b, const SchurLeafArgs& a, hipStream_t s);
+                             const double* Win, int64_t ldwin, int64_t n, int64_t o, int b, const SchurLeafArgs& a,
+                             hipStream_t s);
 hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s);
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,

@@ -797,11 +797,15 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, 0, part, split, cs);
 }
 
-// The fused nested step: Schur update of step p (block [o, o+b)) in place on
-// W (n x n, n < 2048), with the leaf of block q = [qo, qo+qb) (qo a multiple
-// of 64, qb <= 64) into p_next (ld qb) and q's column panel into ct_next.
+// The fused nested step: Schur update of step p (block [o, o+b)) of Win
+// (ld ldwin) into W (ld ldw; Win == W in place), n x n with n < 2048, with
+// the leaf of block q = [qo, qo+qb) (qo a multiple of 64, qb <= 64) into
+// p_next (ld qb) and q's column panel into ct_next.  Every element of W is
+// written, so the first step can read the pivot block where it lies and write
+// the working copy.
 hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw,
-                             int64_t n, int64_t o, int b, const SchurLeafArgs& a, hipStream_t s) {
+                             const double* Win, int64_t ldwin, int64_t n, int64_t o, int b, const SchurLeafArgs& a,
+                             hipStream_t s) {
   if (n <= 0 || n >= 2048 || a.qo % 64 != 0 || a.qb <= 0 || a.qb > 64 || a.qo + a.qb > n || b <= 0)
     return hipErrorInvalidValue;
   StepArgs g;
@@ -809,7 +813,7 @@ hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int
   g.A = Ct; g.lda = ldc;
   g.B = R; g.ldb = ldr;
   g.W = W; g.ldw = ldw;
-  g.Win = W; g.ldwin = ldw;
+  g.Win = Win; g.ldwin = ldwin;
   g.R = R; g.ldr = ldr;
   g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
   const int64_t TT = (n + 63) / 64;
