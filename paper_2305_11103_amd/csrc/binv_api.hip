@@ -443,7 +443,7 @@ binv_status residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, 
 // the error is spread over the rows (a sample of rows is not: where a few rows
 // carry most of the error it can miss them).  It costs two n x n x kProbes
 // products (4 kProbes n^2 flops) instead of the full residual's 2 n^3.  Res
-// needs 3 kProbes n doubles, which the n^2 of the full residual cover once
+// (n^2 doubles) holds the probes and the products' partial slices once
 // n >= kProbeMinN; below that the full residual is cheaper anyway.
 constexpr int kProbes = 64;
 constexpr int64_t kProbeMinN = 3 * kProbes;
@@ -451,12 +451,8 @@ constexpr uint64_t kProbeSeed = 0x243F6A8885A308D3ull;
 
 binv_status probe_residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
                                 double* Res, hipStream_t s, double* rho) {
-  double* Z = Res;
-  double* Zn = Res + (int64_t)kProbes * n;
-  double* Y = Res + 2 * (int64_t)kProbes * n;
-  HIP_TRY(binv::launch_probe_residual(A, lda, X, ldx, n, kProbes, Z, Zn, Y, kProbeSeed ^ (uint64_t)n, s));
   double* part = (double*)c->mx_part.p;
-  HIP_TRY(binv::launch_sumsq(Z, kProbes, n, kProbes, part, part + binv::kSumPartsHost, s));
+  HIP_TRY(binv::launch_probe_residual(A, lda, X, ldx, n, Res, kProbeSeed ^ (uint64_t)n, part, binv::kSumPartsHost, s));
   double h = 0.0;
   HIP_TRY(hipMemcpyAsync(&h, part + binv::kSumPartsHost, sizeof(h), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -113,8 +113,8 @@ hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipS
 
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);
-hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n, int k,
-                                 double* Z, double* Zn, double* Y, uint64_t seed, hipStream_t s);
+hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n,
+                                 double* work, uint64_t seed, double* part, int kParts, hipStream_t s);
 constexpr int kModeResid = 2;  // C = I - A B
 constexpr int kModeAdd = 3;    // C = Cin + A B
 
@@ -132,6 +132,7 @@ hipError_t launch_schur_f32(const float* Ct, int64_t ldc, const float* R, int64_
 hipError_t launch_sumsq(const double* R, int64_t ldr, int64_t rows, int64_t cols, double* part, double* out,
                         hipStream_t s);
 constexpr int kSumPartsHost = 1024;
+hipError_t launch_sum_final(const double* part, int np, double* out, hipStream_t s);
 
 // batched.hip
 constexpr int kSmallVariants = 4;  // most launch shapes of a small tier (autotuned)

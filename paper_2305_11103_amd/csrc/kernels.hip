@@ -697,7 +697,7 @@ static double step_flops(const StepArgs& g, int mode) {
 // remaining 1 - `split` of the positions of every XCD's tile range.
 template <int MODE, int BM, int BN, bool AK, int NWM = 2, int NWN = 2>
 static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo, int qb, double* flops,
-                              int slots = 0, int part = 0, double split = 1.0, const ColSave* cs = nullptr) {
+                              int part = 0, double split = 1.0, const ColSave* cs = nullptr) {
   using C = TileCfg<BM, BN, NWM, NWN>;
   constexpr int BK = C::BK;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
@@ -729,7 +729,6 @@ static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo,
   }
   if (flops) *flops = step_flops<BM, BN>(g, MODE);
   int64_t G = 8 * (g.w1 ? g.w1 - g.w0 : T8);  // multiple of 8 for the XCD-aware tile order
-  if (slots > 0 && G > slots) G = (int64_t)slots / 8 * 8;
   if (G < 8) G = 8;
   const bool vec = (g.M % BM == 0) && (g.N % BN == 0) && (g.K % BK == 0) && ((g.lda & 1) == 0) &&
                    ((g.ldb & 1) == 0) && ((((uintptr_t)g.A) & 15) == 0) && ((((uintptr_t)g.B) & 15) == 0);
@@ -790,11 +789,11 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
     const int64_t tile = schur_tile(n);
     const int64_t a0 = qo / tile * tile;
     const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
-    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 0, 1.0, cs);
+    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 1.0, cs);
   }
   if (schur_tile(n) == 128)
-    return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, 0, part, split, cs);
-  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, 0, part, split, cs);
+    return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, part, split, cs);
+  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, part, split, cs);
 }
 
 // The fused nested step: Schur update of step p (block [o, o+b)) of Win
@@ -842,35 +841,118 @@ hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double*
   return launch_step<MODE_ADD, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
 }
 
-// The probed residual E = Z - A X Z (n x k, ld = k) for k random sign
-// columns Z: Z and Zn = -Z are drawn into Z and Zn, Y = X Zn, then E = Z + A Y
-// in place of Z.  Every row of A X - I contributes to every column of E, so
-// the mean of ||E[:, j]||^2 over the probes is an unbiased estimate of
-// ||A X - I||_F^2 whatever the distribution of the error over the rows.
-hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n, int k,
-                                 double* Z, double* Zn, double* Y, uint64_t seed, hipStream_t s) {
-  if (n <= 0 || k <= 0) return hipSuccess;
+// Skinny product with the contraction split over workgroups: part s of the
+// S slices is M[:, s kslice ..) (m-major, ld ldm) times V[s kslice .., :]
+// (n x 64, ld 64), written to parts + s pstride (n x 64, ld 64).  Workgroup
+// (t, s) computes row tile t of slice s.
+template <bool VEC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_skinny_splitk(const double* __restrict__ Mx, int64_t ldm, const double* __restrict__ V, int64_t n, int64_t kslice,
+                double* __restrict__ parts, int64_t pstride) {
+  using C = TileCfg<64, 64, 2, 2>;
+  __shared__ double As[2][C::BK * C::LA];
+  __shared__ double Bs[2][C::BK * C::LB];
+  const int64_t TM = (n + 63) / 64;
+  const int64_t t = blockIdx.x % TM, sl = blockIdx.x / TM;
+  const int64_t k0 = sl * kslice;
+  StepArgs g;
+  g.A = Mx + k0; g.lda = ldm;
+  g.B = V + k0 * 64; g.ldb = 64;
+  g.W = parts + sl * pstride; g.ldw = 64;
+  g.Win = nullptr; g.ldwin = 0;
+  g.R = nullptr; g.ldr = 0;
+  g.M = n; g.N = 64;
+  g.K = (int)((n - k0 < kslice) ? n - k0 : kslice);
+  g.o = 0; g.b = 0;
+  gemm_tile<MODE_ROW, C, false, VEC>(g, t, 0, As, Bs);
+}
+
+// out[e] = sum over s of parts[s pstride + e], in the order s = 0, 1, ...
+__global__ void __launch_bounds__(256) k_sum_slices(const double* __restrict__ parts, int S, int64_t pstride,
+                                                    int64_t count, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int sl = 0; sl < S; ++sl) v += parts[sl * pstride + e];
+    out[e] = v;
+  }
+}
+
+// Per-workgroup partial sums of (Z[e] + sum over s of parts[s pstride + e])^2.
+__global__ void __launch_bounds__(256) k_probe_sumsq(const double* __restrict__ Z, const double* __restrict__ parts,
+                                                     int S, int64_t pstride, int64_t count, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+    double v = Z[e];
+    for (int sl = 0; sl < S; ++sl) v += parts[sl * pstride + e];
+    acc = fma(v, v, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ||Z - A X Z||_F^2 into *out for 64 random sign columns Z (the probed
+// residual E = Z + A Y with Y = X Zn, Zn = -Z): Z and Zn are drawn into the
+// workspace, Y = X Zn and A Y are formed with the contraction split over about
+// 512 workgroups (both products have only n / 64 row tiles), the slices are
+// summed in a fixed order, and E is reduced as it is formed.  Every row of
+// A X - I contributes to every column of E, so ||E||_F^2 / 64 is an unbiased
+// estimate of ||A X - I||_F^2 whatever the distribution of the error over the
+// rows.  work: 3 * 64 n doubles with one slice, (3 + S) 64 n with S >= 2
+// slices (S <= n / 64 - 3), so n^2 doubles suffice for n >= 192; part:
+// kParts + 1 doubles, the result in part[kParts].
+hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n,
+                                 double* work, uint64_t seed, double* part, int kParts, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  constexpr int k = 64;
   const int64_t count = n * k;
+  double* Z = work;
+  double* Zn = work + count;
+  double* Y = work + 2 * count;
+  double* parts = work + 3 * count;
+  const int64_t TM = (n + 63) / 64;
+  int64_t S = (512 + TM - 1) / TM;
+  const int64_t smax = n / 64 - 3 > 1 ? n / 64 - 3 : 1;
+  if (S > smax) S = smax;
+  int64_t kslice = (n + S - 1) / S;
+  kslice = (kslice + 63) / 64 * 64;
+  S = (n + kslice - 1) / kslice;
   const int64_t gz = (count + 255) / 256;
-  hipLaunchKernelGGL(k_sign_probes, dim3((unsigned)(gz < 1024 ? gz : 1024)), dim3(256), 0, s, Z, Zn, count, seed);
+  const unsigned gr = (unsigned)(gz < 1024 ? gz : 1024);
+  hipLaunchKernelGGL(k_sign_probes, dim3(gr), dim3(256), 0, s, Z, Zn, count, seed);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  StepArgs g;
-  std::memset(&g, 0, sizeof(g));
-  // Y = X Zn: the row-panel product with an empty block (no copied columns)
-  g.A = X; g.lda = ldx;
-  g.B = Zn; g.ldb = k;
-  g.W = Y; g.ldw = k;
-  g.M = n; g.N = k; g.K = (int)n; g.o = 0; g.b = 0;
-  if ((e = launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, nullptr)) != hipSuccess) return e;
-  // E = Z + A Y, in place
-  std::memset(&g, 0, sizeof(g));
-  g.A = A; g.lda = lda;
-  g.B = Y; g.ldb = k;
-  g.W = Z; g.ldw = k;
-  g.Win = Z; g.ldwin = k;
-  g.M = n; g.N = k; g.K = (int)n; g.o = 0; g.b = 0;
-  return launch_step<MODE_ADD, 64, 64, false>(g, s, 0, 0, 0, nullptr);
+  const bool vec = (n % 64 == 0) && ((lda & 1) == 0) && ((ldx & 1) == 0) && ((((uintptr_t)A) & 15) == 0) &&
+                   ((((uintptr_t)X) & 15) == 0);
+  const dim3 grid((unsigned)(TM * S));
+  // with one slice the products need no partial buffers: X Zn goes straight
+  // to Y and A Y to Zn's place (3 * 64 n doubles in all)
+  double* p1 = S == 1 ? Y : parts;
+  double* p2 = S == 1 ? Zn : parts;
+  // Y = X Zn
+  if (vec)
+    hipLaunchKernelGGL(k_skinny_splitk<true>, grid, dim3(256), 0, s, X, ldx, Zn, n, kslice, p1, count);
+  else
+    hipLaunchKernelGGL(k_skinny_splitk<false>, grid, dim3(256), 0, s, X, ldx, Zn, n, kslice, p1, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (S > 1) {
+    hipLaunchKernelGGL(k_sum_slices, dim3(gr), dim3(256), 0, s, parts, (int)S, count, count, Y);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // A Y, then ||Z + A Y||^2
+  if (vec)
+    hipLaunchKernelGGL(k_skinny_splitk<true>, grid, dim3(256), 0, s, A, lda, Y, n, kslice, p2, count);
+  else
+    hipLaunchKernelGGL(k_skinny_splitk<false>, grid, dim3(256), 0, s, A, lda, Y, n, kslice, p2, count);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_probe_sumsq, dim3((unsigned)kParts), dim3(256), 0, s, Z, p2, (int)S, count, count, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_sum_final(part, kParts, part + kParts, s);
 }
 
 // ---------------------------------------------------------------------------

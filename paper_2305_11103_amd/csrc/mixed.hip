@@ -225,6 +225,11 @@ __global__ void __launch_bounds__(256) k_sum_final(const double* __restrict__ pa
 
 constexpr int kSumParts = 1024;
 
+hipError_t launch_sum_final(const double* part, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, part, np, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_f64_to_f32(const double* S, int64_t lds, float* D, int64_t ldd, int64_t rows, int64_t cols,
                              hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
