@@ -77,14 +77,14 @@ typedef enum {
                              a HIP graph on first use and replay it (re-captured
                              when the A, X or info pointers change) */
 #define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only.
-                             By default, block p+1's row/column band is updated
+                             By default, block p+1's diagonal block is updated
                              first, then block p+1's pivot block is inverted
-                             on an internal stream restricted to a few CUs
-                             while the rest of block p's trailing update runs
-                             on another internal stream restricted to the
-                             other CUs; both join back to the caller's stream
-                             before the call's work ends.  Results are bitwise
-                             identical either way. */
+                             on an internal side stream while the rest of block
+                             p's trailing update runs on a second internal
+                             stream (CU-masked only if BINV_SIDE_NCU asks for
+                             it, see binv_lookahead_cus); the caller's stream
+                             waits for both before the call's work ends.
+                             Results are bitwise identical either way. */
 
 typedef struct {
   int32_t k;            /* number of diagonal blocks when `part` is given */
