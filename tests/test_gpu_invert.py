@@ -47,6 +47,9 @@ def test_diag_dominant_256_4x4_blocks(gpu):
 @pytest.mark.parametrize("n,part", [
     (1, None), (2, [1, 1]), (5, [2, 3]), (63, [63]), (65, [64, 1]), (130, [128, 2]),
     (300, [64, 64, 64, 64, 44]), (517, None), (1000, [200, 300, 500]), (777, [7] * 111),
+    # pivot blocks at the fused nested sweep's bounds: 129 (sub-blocks 64, 64,
+    # 1), 2047 (the largest it takes) and 2048 (the copy-and-sweep path)
+    (131, [129, 2]), (2100, [2047, 53]), (2100, [2048, 52]),
 ])
 def test_ragged_partitions(gpu, n, part):
     A = wl.diag_dominant(n, 1000 + n)
