@@ -52,7 +52,8 @@ using binv::PhaseTimer;
 namespace {
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
-                  hipStream_t s, long long* info, int64_t row0, bool lookahead);
+                  hipStream_t s, long long* info, int64_t row0, bool lookahead, const double* src0 = nullptr,
+                  int64_t ldsrc0 = 0);
 
 // Order of the sub-blocks of the nested sweep that inverts a pivot block
 // larger than one leaf (BINV_SUB_BLOCK may set 32, 64 or 128).
@@ -129,8 +130,8 @@ binv_status invert_pivot(binv_ctx* c, int level, const double* Wpp, int64_t ldw,
 }
 
 // Pivot inversion of block [o, o+b) into panel set `buf`, on stream s.
-binv_status block_pivot(binv_ctx* c, int level, double* W, int64_t ldw, int64_t o, int b, int buf, hipStream_t s,
-                        long long* info, int64_t row0) {
+binv_status block_pivot(binv_ctx* c, int level, const double* W, int64_t ldw, int64_t o, int b, int buf,
+                        hipStream_t s, long long* info, int64_t row0) {
   PhaseTimer t(c, level, BINV_PHASE_PIVOT, s);
   return invert_pivot(c, level, W + o * ldw + o, ldw, b, (double*)c->lv[level].p[buf].p, s, info, row0 + o);
 }
@@ -211,8 +212,12 @@ binv_status ensure_side(binv_ctx* c) {
   return BINV_OK;
 }
 
+// src0 (lookahead only): where the caller's out-of-place copy into W takes
+// W from; block 0's pivot block is then read there, on the side stream,
+// beside that copy (the caller recorded ev_fork on s before the copy).
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
-                  hipStream_t s, long long* info, int64_t row0, bool lookahead) {
+                  hipStream_t s, long long* info, int64_t row0, bool lookahead, const double* src0,
+                  int64_t ldsrc0) {
   int bmax = 0;
   for (int32_t b : part) bmax = std::max(bmax, (int)b);
   const int k = (int)part.size();
@@ -251,7 +256,14 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
   // chain is done.  g waits for the side stream, then forms q's row panel;
   // q's column panel is saved by the launches that update it.
   const double split = rest_split(c->side_cus > 0);
-  if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) return st;
+  if (src0) {
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    if ((st = block_pivot(c, level, src0, ldsrc0, off[0], part[0], 0, c->side, info, row0)) != BINV_OK) return st;
+    HIP_TRY(hipEventRecord(c->ev_join, c->side));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+  } else if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) {
+    return st;
+  }
   if ((st = block_panels(c, level, n, W, ldw, off[0], part[0], 0, s)) != BINV_OK) return st;
   hipStream_t g = c->gemm;
   HIP_TRY(hipEventRecord(c->ev_fork, s));
@@ -703,12 +715,21 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
   }
   if (n > 0) {
+    const bool look = !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2;
+    // out of place with the lookahead: block 0's pivot inversion reads A and
+    // runs on the side stream beside the copy of A into X
+    const bool early = look && !inplace;
+    if (early) {
+      if ((st = ensure_side(ctx)) != BINV_OK) goto out;
+      hipError_t e = hipEventRecord(ctx->ev_fork, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("fork: ") + hipGetErrorString(e)); goto out; }
+    }
     if (!inplace) {
       PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
     }
-    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, !(flags & BINV_F_NO_LOOKAHEAD));
+    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
     if (st != BINV_OK) goto out;
   }
   if (flags & BINV_F_SYNC) {
