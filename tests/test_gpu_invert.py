@@ -140,6 +140,25 @@ def test_singular_row_reported(gpu):
     assert e.value.row == 41
 
 
+@pytest.mark.parametrize("inplace", [False, True])
+def test_singular_row_in_a_nested_first_block(gpu, inplace):
+    """A zero column inside block 0 of order 200 (inverted by the nested sweep;
+    out of place with the lookahead, beside the copy of A into X): the call is
+    singular and reports the 1-based row of the first zero pivot, as the oracle."""
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 300
+    A = wl.diag_dominant(n, 3)
+    A[:, 137] = 0.0
+    info = torch.zeros(1, dtype=torch.int64, device="cuda")
+    At = torch.from_numpy(A).cuda()
+    with pytest.raises(binv.SingularError):
+        binv.invert(At, part=[200, 100], info=info, inplace=inplace)
+    with pytest.raises(oracle.SingularError) as e:
+        oracle.gj_inverse(A)
+    assert int(info.item()) == e.value.row == 138
+
+
 def test_empty_matrix(gpu):
     import torch
     from paper_2305_11103_amd import binv
