@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "inverse TFLOP/s (2n³) at ‖AX−I‖≤bound vs plain FP64; solves/s + p50/p99 ms"
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 (matrix and vector)
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X dense FP32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "schur_f64_n8192_b512_traffic.json")
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_swept_step_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2305_11103_amd", "csrc", "kernels.hip")
@@ -409,6 +410,7 @@ def bench_mixed(args):
     rows = np.sort(np.random.default_rng(7).choice(n, size=min(args.check_rows, n, 16), replace=False))
     results = []
     t_plain_all, t_mixed_all = 0.0, 0.0
+    ideal_all, fl_all = [], []
     for ci, cond in enumerate((1e2, 1e4, 1e6)):
         log(f"bench: generating U diag(s) V^T, n={n}, cond={cond:g} (device QR)")
         A = workloads.general_haar_device(n, workloads.stream_seed(3, ci), cond, dev).contiguous()
@@ -444,6 +446,19 @@ def bench_mixed(args):
         best_plain = t_plain if inf64["rho_steps"][0] <= 1e-10 else t_plain_ref
         t_plain_all += best_plain
         t_mixed_all += t_mixed
+        # roofline of each path: the flops its phases do, each at its MFMA
+        # peak (FP32 sweep at the FP32 rate; FP64 sweep, every full residual
+        # I - A X and every correction X R at the FP64 rate).  Residuals: the
+        # start's, the FP64 sweep's after a fallback, one per Newton-Schulz step.
+        g = 2.0 * n ** 3
+        km, fb = infm["refine_steps"], int(infm["fell_back"])
+        mixed_fl32, mixed_fl64 = g, (g if fb else 0.0) + (1 + fb + km) * g + km * g
+        kp = inf64["refine_steps"]
+        plain_fl64 = g + (1 + kp) * g + kp * g
+        ideal_m = mixed_fl32 / (PEAK_FP32 * 1e12) + mixed_fl64 / (PEAK_FP64 * 1e12)
+        ideal_p = plain_fl64 / (PEAK_FP64 * 1e12)
+        ideal_all.append(ideal_m)
+        fl_all.append(mixed_fl32 + mixed_fl64)
         results.append({"cond": cond, "plain_ms": round(t_plain * 1e3, 2),
                         "plain_rho": inf64["rho_steps"][0],
                         "plain_refined_ms": round(t_plain_ref * 1e3, 2), "plain_refined_rho": inf64["rho"],
@@ -452,6 +467,10 @@ def bench_mixed(args):
                         "mixed_rho_oracle_sampled": rho_m, "plain_refined_rho_oracle_sampled": rho_p,
                         "mixed_steps": infm["refine_steps"], "mixed_fell_back": infm["fell_back"],
                         "mixed_converged": infm["converged"],
+                        "mixed_flops_done": mixed_fl32 + mixed_fl64, "mixed_ideal_ms": round(ideal_m * 1e3, 2),
+                        "mixed_roofline_frac": round(ideal_m / t_mixed, 4),
+                        "plain_refined_ideal_ms": round(ideal_p * 1e3, 2),
+                        "plain_refined_roofline_frac": round(ideal_p / t_plain_ref, 4),
                         "speedup_mixed_vs_plain_at_equal_accuracy": round(best_plain / t_mixed, 3)})
         del A, X, Xm, X64
         torch.cuda.empty_cache()
@@ -472,7 +491,13 @@ def bench_mixed(args):
         "valid": ok,
         "plain_fp64_equal_accuracy_tflops": round(flops / t_plain_all / 1e12, 4),
         "per_cond": results,
-        "roofline": None,
+        # the mixed path over the three matrices: achieved = the flops its
+        # phases did / its time; peak = those flops / their ideal time (each
+        # phase at its own MFMA peak), so frac = ideal time / measured time
+        "roofline": {"bound": "mfma", "kernel": "mixed path (FP32 sweep, FP64 pivots, FP64 residual and correction GEMMs)",
+                     "achieved": round(sum(fl_all) / t_mixed_all / 1e12, 3),
+                     "peak": round(sum(fl_all) / sum(ideal_all) / 1e12, 3), "unit": "TFLOP/s",
+                     "frac": round(sum(ideal_all) / t_mixed_all, 4), "traffic": None},
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
