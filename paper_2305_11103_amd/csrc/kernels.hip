@@ -375,6 +375,65 @@ struct TileCfg {
   static constexpr int LB = BN + PAD;
 };
 
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Direct global -> LDS staging of one K-chunk of a 128 x 128 tile's operands
+// (A k-major, B row-major, both full tiles): each wave instruction moves one
+// 128-double row of the chunk, 64 lanes x 16 bytes, into its padded LDS row,
+// so the chunk needs no staging registers and no LDS stores.  The transfer is
+// written as inline assembly because the compiler's builtin for it makes every
+// later LDS read wait for the transfer, which would serialize the prefetch
+// with the multiply of the chunk before it.  The instruction writes no
+// register; M0 (the LDS row address) is set one wait state ahead of it; the
+// caller waits for the transfer (vmcnt) before the barrier that publishes the
+// buffer, and reads the buffer only after that barrier.
+template <class C>
+__device__ __forceinline__ void dl_issue(double* __restrict__ an, double* __restrict__ bn, const StepArgs& g,
+                                         int64_t m0, int64_t n0, int k0) {
+  constexpr int NW = C::NT / 64;
+  static_assert(C::BM == 128 && C::BN == 128 && C::BK % NW == 0, "one 128-double row per wave instruction");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < C::BK / NW; ++e) {
+    const int kk = wave + e * NW;
+    const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)(an + kk * C::LA));
+    const uint32_t lb = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)(bn + kk * C::LB));
+    const double* pa = g.A + (int64_t)(k0 + kk) * g.lda + m0 + 2 * lane;
+    const double* pb = g.B + (int64_t)(k0 + kk) * g.ldb + n0 + 2 * lane;
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(la), "v"(pa) : "memory", "m0");
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lb), "v"(pb) : "memory", "m0");
+  }
+}
+
+// One K-chunk with direct staging: start the next chunk's transfer into
+// (an, bn), multiply the chunk in (as, bs), then wait for this wave's
+// transfer and for the workgroup.
+template <class C, int RG, int CG, int KU>
+__device__ __forceinline__ void dl_chunk(const double* __restrict__ as, const double* __restrict__ bs,
+                                         double* __restrict__ an, double* __restrict__ bn, const StepArgs& g,
+                                         int64_t m0, int64_t n0, int k0next, bool more, double (&acc)[RG][CG]) {
+  constexpr int LA = C::LA, LB = C::LB, BK = C::BK, NWN = C::NWN;
+  constexpr int WM = C::BM / C::NWM, WN = C::BN / C::NWN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / NWN, wn = wave % NWN;
+  const int lk = lane >> 4, lm = lane & 3, ln = lane & 15;
+  if (more) dl_issue<C>(an, bn, g, m0, n0, k0next);
+#pragma unroll KU
+  for (int k4 = 0; k4 < BK / 4; ++k4) {
+    double fb[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) fb[c] = bs[(k4 * 4 + lk) * LB + wn * WN + c * 16 + ln];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const double fa = as[(k4 * 4 + lk) * LA + wm * WM + r * 4 + lm];
+#pragma unroll
+      for (int c = 0; c < CG; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa, fb[c], acc[r][c], 0, 0, 0);
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+}
+
 // One output tile (tm, tn) of a step GEMM.
 // With CS (Schur update only), elements of columns [cs0, cs0 + csb) are also
 // stored transposed into cs (cs[(j - cs0) ldcs + i]): the next block's saved
@@ -504,32 +563,48 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
       }
     };
 
-    gload(0);
-    sstore(0);
-    __syncthreads();
     const int lk = lane >> 4;       // k row this lane feeds
     const int lm = lane & 3;        // A row within a 4-row group
     const int ln = lane & 15;       // B column within a 16-column group
-    for (int kc = 0; kc < nk; ++kc) {
-      const int buf = kc & 1;
-      if (kc + 1 < nk) gload(kc + 1);
-      const double* as = &As[buf][0];
-      const double* bs = &Bs[buf][0];
-#pragma unroll KU
-      for (int k4 = 0; k4 < BK / 4; ++k4) {
-        double fb[CG];
-#pragma unroll
-        for (int c = 0; c < CG; ++c) fb[c] = bs[(k4 * 4 + lk) * LB + wn * WN + c * 16 + ln];
-#pragma unroll
-        for (int r = 0; r < RG; ++r) {
-          const double fa = as[(k4 * 4 + lk) * LA + wm * WM + r * 4 + lm];
-#pragma unroll
-          for (int c = 0; c < CG; ++c)
-            acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa, fb[c], acc[r][c], 0, 0, 0);
-        }
-      }
-      if (kc + 1 < nk) sstore(buf ^ 1);
+    // the trailing update's 128 x 128 full tiles stage their operands
+    // directly into LDS; the other shapes go through registers
+    constexpr bool DL = VEC && A_KMAJOR && BM == 128 && BN == 128 && NT == 512;
+    if constexpr (DL) {
+      dl_issue<C>(&As[0][0], &Bs[0][0], g, m0, n0, 0);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      int kc = 0;
+      for (; kc + 1 < nk; kc += 2) {
+        dl_chunk<C, RG, CG, KU>(&As[0][0], &Bs[0][0], &As[1][0], &Bs[1][0], g, m0, n0, (kc + 1) * BK, true, acc);
+        dl_chunk<C, RG, CG, KU>(&As[1][0], &Bs[1][0], &As[0][0], &Bs[0][0], g, m0, n0, (kc + 2) * BK, kc + 2 < nk,
+                                acc);
+      }
+      if (kc < nk) dl_chunk<C, RG, CG, KU>(&As[0][0], &Bs[0][0], &As[1][0], &Bs[1][0], g, m0, n0, 0, false, acc);
+    } else {
+      gload(0);
+      sstore(0);
+      __syncthreads();
+      for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) gload(kc + 1);
+        const double* as = &As[buf][0];
+        const double* bs = &Bs[buf][0];
+#pragma unroll KU
+        for (int k4 = 0; k4 < BK / 4; ++k4) {
+          double fb[CG];
+#pragma unroll
+          for (int c = 0; c < CG; ++c) fb[c] = bs[(k4 * 4 + lk) * LB + wn * WN + c * 16 + ln];
+#pragma unroll
+          for (int r = 0; r < RG; ++r) {
+            const double fa = as[(k4 * 4 + lk) * LA + wm * WM + r * 4 + lm];
+#pragma unroll
+            for (int c = 0; c < CG; ++c)
+              acc[r][c] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa, fb[c], acc[r][c], 0, 0, 0);
+          }
+        }
+        if (kc + 1 < nk) sstore(buf ^ 1);
+        __syncthreads();
+      }
     }
   }
 
