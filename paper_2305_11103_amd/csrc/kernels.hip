@@ -669,6 +669,10 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) k_gemm_step(StepArgs g, Col
 template <bool VEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_schur_leaf(StepArgs g, SchurLeafArgs a) {
+  // the nested sweep is the pivot chain that runs beside the trailing update
+  // and gates the next step: its waves issue ahead of the update's on shared
+  // CUs (a wave priority, not a stream priority)
+  __builtin_amdgcn_s_setprio(3);
   using C = TileCfg<64, 64, 2, 2>;
   static_assert(C::NT == 256, "the leaf runs on the tile's 4 waves");
   __shared__ double As[2][C::BK * C::LA];

@@ -50,6 +50,10 @@ def test_diag_dominant_256_4x4_blocks(gpu):
     # pivot blocks at the fused nested sweep's bounds: 129 (sub-blocks 64, 64,
     # 1), 2047 (the largest it takes) and 2048 (the copy-and-sweep path)
     (131, [129, 2]), (2100, [2047, 53]), (2100, [2048, 52]),
+    # full 128 x 128 trailing-update tiles (operands staged straight into LDS)
+    # with 1, 2, 3, 13 and 109 K-chunks of 16: odd counts end on the
+    # single-chunk tail of the two-buffer loop
+    (2048, [16, 32, 48, 208, 1744]),
 ])
 def test_ragged_partitions(gpu, n, part):
     A = wl.diag_dominant(n, 1000 + n)
