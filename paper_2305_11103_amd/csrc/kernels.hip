@@ -866,12 +866,13 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
   if (region == 3) {
     // the next block's diagonal tiles of the trailing-update grid, updated
-    // with 64 x 64 tiles (more workgroups for this short launch) over exactly
-    // the element range those grid tiles cover
+    // with 32 x 32 tiles (a 512-block gives 256 workgroups, one per CU, for
+    // this short launch on the critical path) over exactly the element range
+    // those grid tiles cover
     const int64_t tile = schur_tile(n);
     const int64_t a0 = qo / tile * tile;
     const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
-    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 1.0, cs);
+    return launch_step<MODE_SCHUR, 32, 32, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 1.0, cs);
   }
   if (schur_tile(n) == 128)
     return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, part, split, cs);
