@@ -311,7 +311,8 @@ binv_status binv_server_destroy(binv_server* server);
 #define BINV_PHASE_ROW 1     /* row panel GEMM */
 #define BINV_PHASE_SCHUR 2   /* Schur trailing update GEMM (all tiles; under
                                 lookahead all but the next block's diagonal
-                                block, on the CU-masked stream) */
+                                block, on the trailing-update stream, which is
+                                CU-masked only when CUs are reserved) */
 #define BINV_PHASE_OTHER 3   /* copies and panel saves */
 #define BINV_PHASE_BAND 4    /* lookahead: Schur update of the next block's
                                 diagonal block, before the fork */
