@@ -17,6 +17,11 @@ it with gcc and marshals numpy arrays through ctypes.
                                 block (first half of Eq. (a)).
   residual_rows(A, X, rows)     Rows of A X - I with compensated dot products.
   residual_stats(A, X)          rho = ||AX-I||_F / sqrt(n) and max |AX-I|.
+  block_gj_inverse(A, part, pivot)
+                                Block Gauss-Jordan over the partition (Eq. (a)
+                                unrolled, §4.2): without pivoting across blocks
+                                (pivot=False) or with block-row pivoting by
+                                tournament selection (pivot=True).
   ns_step(A, X)                 One Newton-Schulz step X + X (I - A X).
   matmul(A, B)                  Plain product.
 """
@@ -75,6 +80,8 @@ def _load():
     lib.orc_ns_step.restype = i64
     lib.orc_matmul.argtypes = [i64, i64, i64, P, P, P]
     lib.orc_matmul.restype = None
+    lib.orc_block_gj.argtypes = [i64, P, i32, P, i32, i32, i32, i32, P, P]
+    lib.orc_block_gj.restype = i64
     _lib = lib
     return lib
 
@@ -166,6 +173,36 @@ def residual_stats(A, X, rows=None) -> dict:
     fro2 = float(np.sum(R * R))
     rho = np.sqrt(fro2 * (n / m) / n)
     return {"rho": float(rho), "rho_max": float(np.max(np.abs(R))), "rows": int(m)}
+
+
+def block_gj_inverse(A, part=None, pivot: bool = False, sub: int = 64, leaf_rows: int = 256,
+                     arity: int = 4, return_perm: bool = False):
+    """Block Gauss-Jordan over the diagonal blocks `part` (one block of order n
+    when None), the two readings of oracle.c's orc_block_gj: pivot=False pivots
+    only inside pivot blocks (leaves of `sub` rows for blocks above 128);
+    pivot=True picks each block's pivot rows among all rows below by tournament
+    selection (`sub`-wide strips, leaves of `leaf_rows` rows, `arity` nodes per
+    merge).  return_perm: also the final row order (original row at each
+    position)."""
+    A = _square(A)
+    n = A.shape[0]
+    X = np.zeros_like(A)
+    if part is None:
+        p = None
+        k = 0
+    else:
+        p = np.ascontiguousarray(part, dtype=np.int32)
+        k = int(p.size)
+        if k == 0 or int(p.sum()) != n or (p <= 0).any():
+            raise ValueError(f"partition {list(p)} does not split order {n}")
+    perm = np.zeros(max(n, 1), dtype=np.int64)
+    info = _load().orc_block_gj(n, _ptr(A), k, _ptr(p) if p is not None else None, int(bool(pivot)), int(sub),
+                                int(leaf_rows), int(arity), _ptr(X), _ptr(perm))
+    if info > 0:
+        raise SingularError(info)
+    if info < 0:
+        raise ValueError("invalid arguments or allocation failure")
+    return (X, perm[:n]) if return_perm else X
 
 
 def ns_step(A, X) -> np.ndarray:

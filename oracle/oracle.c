@@ -25,6 +25,11 @@
  *                          is measured at about twice working precision.
  *   orc_ns_step            One Newton-Schulz step X + X (I - A X), plain FP64.
  *   orc_matmul             C = A B, plain i-k-j loop (for pins and tests).
+ *   orc_block_gj           Block Gauss-Jordan over a partition (Eq. (a)
+ *                          unrolled one diagonal block at a time, §4.2),
+ *                          without pivoting across blocks or with block-row
+ *                          pivoting by tournament selection: the two readings
+ *                          the GPU path implements (see its comment).
  *
  * Singularity convention: a pivot (or a leaf determinant) that is exactly 0.0
  * makes the routine return the 1-based global row concerned; 0 means success.
@@ -345,4 +350,297 @@ int64_t orc_ns_step(int64_t n, const double* A, const double* X, double* Xnext) 
   mm(n, n, n, 1.0, X, n, R, n, X, n, Xnext, n);
   free(R);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O6: block Gauss-Jordan over a partition, in the two readings the GPU      */
+/* path implements.  Test infrastructure: it follows the steps of the        */
+/* unrolled in-place Eq. (a) (§3, §4.2) one diagonal block at a time, in     */
+/* plain loops, and shares nothing with the HIP code.                        */
+/*                                                                           */
+/* pivot = 0  (the paper's method: no pivoting across blocks, §3)            */
+/*   P = W_pp^-1: Gauss-Jordan with partial pivoting inside the block when   */
+/*       b <= 128, else block Gauss-Jordan on the block with `sub`-wide      */
+/*       sub-blocks, each sub-block's leaf inverted by Gauss-Jordan with     */
+/*       partial pivoting inside that leaf;                                  */
+/*   R = P W[p, :] with R[:, p] = P (row panel);                             */
+/*   W[i, j] -= W[i, p] R[:, j] (j outside p), W[i, p] = -W[i, p] P          */
+/*       for every row i outside p, then W[p, :] = R.                        */
+/*                                                                           */
+/* pivot = 1  (block-row pivoting, the re-blocking remedy of §3 taken to     */
+/*   rows: the counter-diagonal Eqs. (b)/(c) are Eq. (a) on a block-row      */
+/*   permuted matrix; here the rows that form the pivot block are chosen):   */
+/*   - the b pivot rows come from rows o..n-1 by tournament selection over   */
+/*     `sub`-wide column strips of the block's current columns: leaves are   */
+/*     chunks of `leaf_rows` consecutive rows (rows already chosen left      */
+/*     out), each node keeps the rows Gauss elimination with partial         */
+/*     pivoting picks among its candidates (the lowest candidate position    */
+/*     wins ties), `arity` consecutive nodes merge into one, and the root's  */
+/*     picks in pick order are the strip's pivot rows; the strip is then     */
+/*     eliminated from the block's later columns of every row (through the   */
+/*     inverse of the picked rows' strip block, Gauss-Jordan with partial    */
+/*     pivoting);                                                            */
+/*   - the picked rows move to positions o..o+b-1 in pick order, the rows    */
+/*     they displace take the vacated positions in ascending order;          */
+/*   - R = the pivot rows after block Gauss-Jordan with `sub`-wide           */
+/*     sub-blocks on their b x b block, applied to all n columns (so R's     */
+/*     p columns hold P and the others P W[p, :] formed by the same          */
+/*     sub-block row operations);                                            */
+/*   - the update of the other rows as above;                                */
+/*   - at the end, column perm[c] of X is column c of W (perm[c] = the       */
+/*     original row at position c), which undoes the row moves.              */
+/* Returns 0, the 1-based row (pivot position) of an exactly-zero pivot, or  */
+/* < 0 on bad arguments.  perm_out (may be NULL): the final row order.       */
+/* ------------------------------------------------------------------------ */
+
+/* Gauss elimination with partial pivoting on the nc candidate rows cand[] of
+ * the panel T (rows indexed from o, ld ldt) over columns [c0, c0 + w).
+ * Writes up to w picked rows (in pick order) to win[] and returns how many;
+ * *zero (if not NULL) becomes the first column index whose pick had a zero
+ * value, else -1. */
+static int64_t gepp_pick(int64_t nc, const int64_t* cand, const double* T, int64_t ldt, int64_t o, int64_t c0,
+                         int64_t w, int64_t* win, int64_t* zero) {
+  double* V = (double*)malloc(sizeof(double) * (size_t)(nc * w + 1));
+  char* used = (char*)calloc((size_t)nc + 1, 1);
+  int64_t got = 0;
+  if (zero) *zero = -1;
+  for (int64_t i = 0; i < nc; ++i)
+    for (int64_t j = 0; j < w; ++j) V[i * w + j] = T[IDX(cand[i] - o, c0 + j, ldt)];
+  for (int64_t c = 0; c < w && got < nc; ++c) {
+    int64_t r = -1;
+    double best = -1.0;
+    for (int64_t i = 0; i < nc; ++i) {
+      if (used[i]) continue;
+      double v = fabs(V[i * w + c]);
+      if (v > best) { best = v; r = i; }
+    }
+    if (r < 0) break;
+    used[r] = 1;
+    win[got++] = cand[r];
+    double pv = V[r * w + c];
+    if (pv == 0.0) {
+      if (zero && *zero < 0) *zero = c;
+      continue;
+    }
+    double q = 1.0 / pv;
+    for (int64_t i = 0; i < nc; ++i) {
+      if (used[i]) continue;
+      double l = V[i * w + c] * q;
+      for (int64_t j = c + 1; j < w; ++j) V[i * w + j] -= l * V[r * w + j];
+    }
+  }
+  free(V); free(used);
+  return got;
+}
+
+/* Tournament over rows [o, n) not yet chosen (chosen_flag[row - o] != 0),
+ * strip [c0, c0 + w) of the panel T.  Writes the w root picks to out[] and
+ * returns the root's first zero-pivot column (or -1). */
+static int64_t tournament(const double* T, int64_t ldt, int64_t o, int64_t n, const char* chosen_flag, int64_t c0,
+                          int64_t w, int64_t leaf_rows, int64_t arity, int64_t* out) {
+  int64_t nleaf = (n - o + leaf_rows - 1) / leaf_rows;
+  int64_t* nodes = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nleaf * w + 1));
+  int64_t* ncount = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nleaf + 1));
+  int64_t* cand = (int64_t*)malloc(sizeof(int64_t) * (size_t)((leaf_rows > arity * w ? leaf_rows : arity * w) + 1));
+  int64_t zero = -1;
+  for (int64_t l = 0; l < nleaf; ++l) {
+    int64_t nc = 0;
+    for (int64_t r = o + l * leaf_rows; r < o + (l + 1) * leaf_rows && r < n; ++r)
+      if (!chosen_flag[r - o]) cand[nc++] = r;
+    ncount[l] = gepp_pick(nc, cand, T, ldt, o, c0, w, nodes + l * w, &zero);
+  }
+  int64_t nn = nleaf;
+  while (nn > 1) {
+    int64_t m = (nn + arity - 1) / arity;
+    for (int64_t g = 0; g < m; ++g) {
+      int64_t nc = 0;
+      for (int64_t ch = g * arity; ch < (g + 1) * arity && ch < nn; ++ch)
+        for (int64_t t = 0; t < ncount[ch]; ++t) cand[nc++] = nodes[ch * w + t];
+      /* node g's picks overwrite slot g, which no later group reads */
+      ncount[g] = gepp_pick(nc, cand, T, ldt, o, c0, w, nodes + g * w, &zero);
+    }
+    nn = m;
+  }
+  for (int64_t t = 0; t < w; ++t) out[t] = nodes[t];
+  free(nodes); free(ncount); free(cand);
+  return zero;
+}
+
+/* Block Gauss-Jordan on the b pivot rows M (b x ncols, ld ldm) with their
+ * b x b block at columns [co, co + b): sub-block s (rows and columns
+ * [s0, s0 + sb) of the block) in turn: Q = GJ-PP inverse of its current
+ * leaf, its rows become Q times themselves (their leaf columns Q), every
+ * other row i subtracts (its leaf-column values) times those new rows (its
+ * leaf columns becoming -(values) Q).  Afterwards M[:, co:co+b] = block^-1
+ * and the other columns hold block^-1 times their original values.
+ * Returns 0 or the 1-based row (within the block) of a zero leaf pivot. */
+static int64_t rows_block_gj(int64_t b, double* M, int64_t ldm, int64_t ncols, int64_t co, int64_t sub) {
+  double* leaf = (double*)malloc(sizeof(double) * (size_t)(sub * sub));
+  double* Q = (double*)malloc(sizeof(double) * (size_t)(sub * sub));
+  double* Rj = (double*)malloc(sizeof(double) * (size_t)(sub * ncols));
+  double* c = (double*)malloc(sizeof(double) * (size_t)sub);
+  int64_t info = 0;
+  for (int64_t s0 = 0; s0 < b; s0 += sub) {
+    int64_t sb = b - s0 < sub ? b - s0 : sub;
+    for (int64_t i = 0; i < sb; ++i)
+      for (int64_t j = 0; j < sb; ++j) leaf[i * sb + j] = M[IDX(s0 + i, co + s0 + j, ldm)];
+    int64_t e = orc_gj_inverse(sb, leaf, Q);
+    if (e) { info = s0 + e; break; }
+    /* Rj = Q * M[s0 rows, :], with Q in the leaf columns */
+    for (int64_t i = 0; i < sb; ++i)
+      for (int64_t j = 0; j < ncols; ++j) {
+        double acc = 0.0;
+        for (int64_t t = 0; t < sb; ++t) acc += Q[i * sb + t] * M[IDX(s0 + t, j, ldm)];
+        Rj[i * ncols + j] = acc;
+      }
+    for (int64_t i = 0; i < sb; ++i)
+      for (int64_t j = 0; j < sb; ++j) Rj[i * ncols + co + s0 + j] = Q[i * sb + j];
+    for (int64_t i = 0; i < b; ++i) {
+      if (i >= s0 && i < s0 + sb) continue;
+      for (int64_t t = 0; t < sb; ++t) c[t] = M[IDX(i, co + s0 + t, ldm)];
+      for (int64_t j = 0; j < ncols; ++j) {
+        int in_leaf = (j >= co + s0 && j < co + s0 + sb);
+        double acc = 0.0;
+        for (int64_t t = 0; t < sb; ++t) acc += c[t] * Rj[t * ncols + j];
+        M[IDX(i, j, ldm)] = (in_leaf ? 0.0 : M[IDX(i, j, ldm)]) - acc;
+      }
+    }
+    for (int64_t i = 0; i < sb; ++i)
+      for (int64_t j = 0; j < ncols; ++j) M[IDX(s0 + i, j, ldm)] = Rj[i * ncols + j];
+  }
+  free(leaf); free(Q); free(Rj); free(c);
+  return info;
+}
+
+int64_t orc_block_gj(int64_t n, const double* A, int32_t k, const int32_t* part, int32_t pivot, int32_t sub,
+                     int32_t leaf_rows, int32_t arity, double* X, int64_t* perm_out) {
+  if (n < 0 || sub <= 0 || leaf_rows <= 0 || arity < 2) return -2;
+  if (n == 0) return 0;
+  int32_t one = (int32_t)n;
+  if (!part || k <= 0) { part = &one; k = 1; }
+  int64_t s = 0;
+  for (int32_t i = 0; i < k; ++i) { if (part[i] <= 0) return -2; s += part[i]; }
+  if (s != n) return -2;
+  int64_t bmax = 0;
+  for (int32_t i = 0; i < k; ++i) if (part[i] > bmax) bmax = part[i];
+
+  double* W = (double*)malloc(sizeof(double) * (size_t)(n * n));
+  double* Wn = (double*)malloc(sizeof(double) * (size_t)(n * n));
+  int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t* src = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  double* R = (double*)malloc(sizeof(double) * (size_t)(bmax * n));
+  double* P = (double*)malloc(sizeof(double) * (size_t)(bmax * bmax));
+  double* blk = (double*)malloc(sizeof(double) * (size_t)(bmax * bmax));
+  double* T = (double*)malloc(sizeof(double) * (size_t)(n * bmax));
+  double* Q = (double*)malloc(sizeof(double) * (size_t)(sub * sub));
+  double* G = (double*)malloc(sizeof(double) * (size_t)(sub * bmax));
+  int64_t* chosen = (int64_t*)malloc(sizeof(int64_t) * (size_t)bmax);
+  char* flag = (char*)malloc((size_t)n);
+  int64_t info = -1;
+  if (!W || !Wn || !perm || !src || !R || !P || !blk || !T || !Q || !G || !chosen || !flag) goto done;
+  info = 0;
+  memcpy(W, A, sizeof(double) * (size_t)(n * n));
+  for (int64_t i = 0; i < n; ++i) perm[i] = i;
+
+  int64_t o = 0;
+  for (int32_t p = 0; p < k; o += part[p], ++p) {
+    const int64_t b = part[p];
+    if (pivot) {
+      /* --- choose the b pivot rows among rows o..n-1 --- */
+      const int64_t nr = n - o;
+      for (int64_t i = 0; i < nr; ++i)
+        for (int64_t t = 0; t < b; ++t) T[IDX(i, t, b)] = W[IDX(o + i, o + t, n)];
+      memset(flag, 0, (size_t)nr);
+      for (int64_t c0 = 0; c0 < b; c0 += sub) {
+        const int64_t w = b - c0 < sub ? b - c0 : sub;
+        int64_t z = tournament(T, b, o, n, flag, c0, w, leaf_rows, arity, chosen + c0);
+        if (z >= 0) { info = o + c0 + z + 1; goto done; }
+        for (int64_t t = 0; t < w; ++t) flag[chosen[c0 + t] - o] = 1;
+        const int64_t rest = b - c0 - w;
+        if (rest <= 0) continue;
+        /* eliminate the strip from the block's later columns of every row */
+        for (int64_t i = 0; i < w; ++i)
+          for (int64_t j = 0; j < w; ++j) blk[i * w + j] = T[IDX(chosen[c0 + i] - o, c0 + j, b)];
+        if (orc_gj_inverse(w, blk, Q)) { info = o + c0 + 1; goto done; }
+        for (int64_t i = 0; i < w; ++i)
+          for (int64_t j = 0; j < rest; ++j) {
+            double acc = 0.0;
+            for (int64_t t = 0; t < w; ++t) acc += Q[i * w + t] * T[IDX(chosen[c0 + t] - o, c0 + w + j, b)];
+            G[i * rest + j] = acc;
+          }
+        for (int64_t i = 0; i < nr; ++i)
+          for (int64_t j = 0; j < rest; ++j) {
+            double acc = 0.0;
+            for (int64_t t = 0; t < w; ++t) acc += T[IDX(i, c0 + t, b)] * G[t * rest + j];
+            T[IDX(i, c0 + w + j, b)] -= acc;
+          }
+      }
+      /* --- move: picked rows to o..o+b-1, displaced rows to the vacated slots --- */
+      for (int64_t i = 0; i < n; ++i) src[i] = i;
+      for (int64_t t = 0; t < b; ++t) src[o + t] = chosen[t];
+      {
+        int64_t dpos = o, vrow = o + b;
+        for (;;) {
+          while (dpos < o + b && flag[dpos - o]) ++dpos;   /* next displaced row */
+          while (vrow < n && !flag[vrow - o]) ++vrow;      /* next vacated slot */
+          if (dpos >= o + b || vrow >= n) break;
+          src[vrow] = dpos;
+          ++dpos; ++vrow;
+        }
+      }
+      for (int64_t i = 0; i < n; ++i) memcpy(Wn + i * n, W + src[i] * n, sizeof(double) * (size_t)n);
+      { double* t = W; W = Wn; Wn = t; }
+      for (int64_t i = 0; i < n; ++i) src[i] = perm[src[i]];
+      memcpy(perm, src, sizeof(int64_t) * (size_t)n);
+      /* --- R by block Gauss-Jordan on the pivot rows --- */
+      for (int64_t i = 0; i < b; ++i) memcpy(R + i * n, W + (o + i) * n, sizeof(double) * (size_t)n);
+      int64_t e = rows_block_gj(b, R, n, n, o, sub);
+      if (e) { info = o + e; goto done; }
+      for (int64_t i = 0; i < b; ++i)
+        for (int64_t j = 0; j < b; ++j) P[i * b + j] = R[IDX(i, o + j, n)];
+    } else {
+      for (int64_t i = 0; i < b; ++i)
+        for (int64_t j = 0; j < b; ++j) blk[i * b + j] = W[IDX(o + i, o + j, n)];
+      int64_t e;
+      if (b <= 128) {
+        e = orc_gj_inverse(b, blk, P);
+      } else {
+        e = rows_block_gj(b, blk, b, b, 0, sub);
+        memcpy(P, blk, sizeof(double) * (size_t)(b * b));
+      }
+      if (e) { info = o + e; goto done; }
+      /* R = P W[p, :], R[:, p] = P */
+      for (int64_t i = 0; i < b; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double acc = 0.0;
+          for (int64_t t = 0; t < b; ++t) acc += P[i * b + t] * W[IDX(o + t, j, n)];
+          R[i * n + j] = acc;
+        }
+      for (int64_t i = 0; i < b; ++i)
+        for (int64_t j = 0; j < b; ++j) R[i * n + o + j] = P[i * b + j];
+    }
+    /* --- update every row outside block p, then the pivot rows --- */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      if (i >= o && i < o + b) continue;
+      double* c = (double*)malloc(sizeof(double) * (size_t)b);
+      for (int64_t t = 0; t < b; ++t) c[t] = W[IDX(i, o + t, n)];
+      for (int64_t j = 0; j < n; ++j) {
+        int jp = (j >= o && j < o + b);
+        double acc = 0.0;
+        for (int64_t t = 0; t < b; ++t) acc += c[t] * R[t * n + j];
+        W[IDX(i, j, n)] = (jp ? 0.0 : W[IDX(i, j, n)]) - acc;
+      }
+      free(c);
+    }
+    for (int64_t i = 0; i < b; ++i) memcpy(W + (o + i) * n, R + i * n, sizeof(double) * (size_t)n);
+  }
+  /* undo the row moves: column perm[c] of X is column c of W */
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t c = 0; c < n; ++c) X[IDX(i, perm[c], n)] = W[IDX(i, c, n)];
+  if (perm_out) memcpy(perm_out, perm, sizeof(int64_t) * (size_t)n);
+done:
+  free(W); free(Wn); free(perm); free(src); free(R); free(P); free(blk); free(T); free(Q); free(G);
+  free(chosen); free(flag);
+  return info;
 }

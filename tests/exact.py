@@ -123,3 +123,51 @@ def hilbert_inverse(n: int) -> np.ndarray:
             v = (-1) ** (i + j) * (i + j - 1) * comb(n + i - 1, n - j) * comb(n + j - 1, n - i) * comb(i + j - 2, i - 1) ** 2
             out[i - 1, j - 1] = v
     return out
+
+
+def _tri_inv_frac(T, lower: bool):
+    """Exact inverse of a triangular Fraction matrix by substitution."""
+    n = len(T)
+    X = [[Fraction(0)] * n for _ in range(n)]
+    for j in range(n):
+        rng_i = range(j, n) if lower else range(j, -1, -1)
+        for i in rng_i:
+            if i == j:
+                X[i][j] = 1 / T[i][i]
+                continue
+            ks = range(j, i) if lower else range(i + 1, j + 1)
+            X[i][j] = -sum((T[i][k] * X[k][j] for k in ks), Fraction(0)) / T[i][i]
+    return X
+
+
+def dyadic_plu(n: int, rng, lower: bool = True):
+    """A = Pi L U with small dyadic factors and its exact inverse.
+
+    L: unit lower triangular, off-diagonal entries from {-1/2, 0, 1/2} (so
+    |l| < 1 and partial pivoting meets a unique largest entry in every column:
+    it recovers Pi, L and U exactly); with lower=False, L = I.  U: upper
+    triangular, diagonal from {+-1, +-2}, off-diagonal from {-1, 0, 1}.  Pi: a
+    random row permutation (A[i] = (L U)[pi[i]]).  Every value met by
+    elimination in the pivot order is a short dyadic rational, so FP64
+    elimination in that order is exact.  Returns (A, exact inverse as floats,
+    pi)."""
+    half = Fraction(1, 2)
+    L = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    Uf = [[Fraction(0)] * n for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            if lower and j < i:
+                L[i][j] = half * int(rng.integers(-1, 2))
+            if j > i:
+                Uf[i][j] = Fraction(int(rng.integers(-1, 2)))
+        Uf[i][i] = Fraction(int(rng.choice([-2, -1, 1, 2])))
+    pi = rng.permutation(n)
+    LU = matmul(L, Uf)
+    A = [LU[int(pi[i])] for i in range(n)]
+    # A^-1 = U^-1 L^-1 Pi^T: column pi[i] of (LU)^-1 is column i of A^-1
+    LUi = matmul(_tri_inv_frac(Uf, lower=False), _tri_inv_frac(L, lower=True))
+    Ai = [[LUi[r][int(pi[c])] for c in range(n)] for r in range(n)]
+    Af, Aif = to_float(A), to_float(Ai)
+    assert all(Fraction(float(Af[i, j])) == A[i][j] for i in range(n) for j in range(n))
+    assert all(Fraction(float(Aif[i, j])) == Ai[i][j] for i in range(n) for j in range(n))
+    return Af, Aif, pi

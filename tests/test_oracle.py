@@ -294,6 +294,46 @@ def test_residual_rows_subset():
     assert np.array_equal(oracle.residual_rows(A, X, rows), Rall[rows])
 
 
+def test_residual_stats_is_scaled_identity_error():
+    """A = I, X = (1 + e) I: A X - I = e I, so rho = ||e I||_F / sqrt(n) = e
+    exactly and the largest entry is e (e a power of two: no rounding)."""
+    for n in (1, 5, 64):
+        for e in (2.0 ** -20, 2.0 ** -40):
+            st = oracle.residual_stats(np.eye(n), (1.0 + e) * np.eye(n))
+            assert st["rho"] == e and st["rho_max"] == e and st["rows"] == n
+
+
+def test_residual_stats_sampled_rows_rescale():
+    """A = I, X = diag(1 + e_i): row i of A X - I is e_i e_i^T.  Over rows S
+    the sampled rho is sqrt((n / |S|) sum_S e_i^2 / n) = sqrt(sum_S e_i^2 / |S|)
+    and over all rows sqrt(sum e_i^2 / n); values chosen so both are exact."""
+    e = np.array([2.0 ** -10, 0.0, 3 * 2.0 ** -12, 0.0, 2.0 ** -11, 0.0, 0.0, 4 * 2.0 ** -12])
+    n = e.size
+    X = np.diag(1.0 + e)
+    full = oracle.residual_stats(np.eye(n), X)
+    assert full["rho"] == np.sqrt(np.sum(e * e) / n)
+    rows = [0, 2, 4, 7]
+    samp = oracle.residual_stats(np.eye(n), X, rows)
+    # sum_S e^2 = (16 + 9 + 4 + 16) 2^-24 = 45 2^-24 over 4 rows
+    assert samp["rho"] == np.sqrt(45.0 * 2.0 ** -24 / 4)
+    assert samp["rows"] == 4 and samp["rho_max"] == 2.0 ** -10
+    assert oracle.residual_stats(np.eye(n), X, rows=list(range(n)))["rho"] == full["rho"]
+
+
+@pytest.mark.parametrize("n", [3, 5, 7])
+def test_residual_stats_matches_exact_rational_norm(n):
+    """rho of a perturbed inverse against ||A X - I||_F / sqrt(n) formed in
+    exact rationals (the square root taken once in floating point)."""
+    rng = np.random.default_rng(30 + n)
+    A = rng.integers(-5, 6, size=(n, n)).astype(np.float64) + 6 * np.eye(n)
+    X = np.linalg.inv(A) + 2.0 ** -30 * rng.integers(-3, 4, size=(n, n))
+    Re = exact.sub(exact.matmul(exact.to_frac(A), exact.to_frac(X)), exact.identity(n))
+    fro2 = sum((x * x for row in Re for x in row), Fraction(0))
+    rho_exact = float(fro2 / n) ** 0.5
+    rho = oracle.residual_stats(A, X)["rho"]
+    assert abs(rho - rho_exact) <= 4 * U * rho_exact
+
+
 # --------------------------------------------------------------------------
 # O4: Newton-Schulz step
 # --------------------------------------------------------------------------
