@@ -86,6 +86,27 @@ typedef enum {
                              waits for both before the call's work ends.
                              Results are bitwise identical either way. */
 
+#define BINV_F_PIVOT 32u /* block-row pivoting (binv_invert, and the FP64 sweep of
+                             binv_invert_mixed): the b_p rows that form pivot
+                             block p are chosen among all rows not yet used as
+                             pivots, by tournament selection on the block's
+                             columns (strips of 64 columns; leaves of 256
+                             consecutive rows, each node keeping the rows that
+                             Gauss elimination with partial pivoting picks,
+                             four nodes merging into one); the chosen rows take
+                             the block's position and a final column
+                             permutation undoes the moves.  The row panel is
+                             formed by the pivot block's own 64-wide
+                             Gauss-Jordan sub-steps instead of a product with
+                             its explicit inverse.  This extends the
+                             re-blocking remedy of §3 (Eqs. (b) and (c) are
+                             Eq. (a) on a block-row permuted matrix) to any
+                             non-singular input, the permutation
+                             counter-example of §3 included, with the
+                             residual of Gauss-Jordan with partial pivoting.
+                             Needs every block order <= 2047 and n <= 32768
+                             (BINV_E_INVALID otherwise). */
+
 typedef struct {
   int32_t k;            /* number of diagonal blocks when `part` is given */
   const int32_t* part;  /* host array of k diagonal-block orders summing to n,
@@ -130,14 +151,17 @@ typedef struct {
   double rho;              /* rho of the returned X, computed in FP64 on the GPU */
   double rho_steps[8];     /* rho of each successive iterate: the FP32 sweep's
                               (if it fell back), the starting sweep's, then
-                              after each Newton-Schulz step */
-  int32_t refine_steps;    /* Newton-Schulz steps applied */
+                              after each Newton-Schulz step; a last entry not
+                              below the one before it is a step that was formed
+                              and rejected (X keeps the better iterate) */
+  int32_t refine_steps;    /* Newton-Schulz steps accepted into X */
   int32_t fell_back;       /* 1: the FP32 sweep's rho was >= 0.5 (Newton-Schulz
                               would not converge), so the FP64 sweep was used
                               as the starting point */
   int32_t converged;       /* 1: rho <= target */
   int32_t sampled;         /* 1: rho is the random-probe estimate
                               (BINV_F_SAMPLED_CHECK); 0: the full residual */
+  int32_t rho_count;       /* entries of rho_steps that were filled */
 } binv_info;
 
 /* rho = ||A X - I||_F / sqrt(n) of a given X: the residual norm check (a6 of
@@ -152,8 +176,23 @@ typedef struct {
  * Uses ctx's workspace (n^2 doubles); synchronizes `stream` and writes *rho.
  * Errors: BINV_E_INVALID (NULL pointers, n < 0, ld < n, unknown flags). */
 #define BINV_RESID_ESTIMATE 1u
+#define BINV_RESID_COMPENSATED 2u /* the full residual formed with an error-free
+                             split of the operands (Ozaki, Ogita, Oishi and
+                             Rump 2012): A split by rows and X by columns into a
+                             leading part of (52 - ceil(log2 n)) / 2 bits and
+                             the rest, so that I - A1 X1 is exact in FP64 and
+                             R = (I - A1 X1) - A2 X1 - A X2 carries rounding
+                             errors about 2^-bits of a plain FP64 residual's;
+                             three n^3 FP64 GEMMs, 4 n^2 doubles of extra
+                             workspace.  binv_invert_mixed always forms its
+                             residuals this way. */
 binv_status binv_residual(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
                           uint32_t flags, void* stream, double* rho);
+/* The compensated residual matrix itself: R = I - A X (n x n, ld ldr, device)
+ * as binv_residual forms it with BINV_RESID_COMPENSATED, and rho.  Synchronous.
+ * Errors: BINV_E_INVALID (NULL pointers, n < 0, ld < n). */
+binv_status binv_residual_matrix(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, const double* X,
+                                 int64_t ldx, double* R, int64_t ldr, void* stream, double* rho);
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
  * is read again by the refinement.  opts: the partition (as binv_invert) and

@@ -28,7 +28,7 @@ BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
 EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
-           "binv_invert_mixed", "binv_residual",
+           "binv_invert_mixed", "binv_residual", "binv_residual_matrix",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
            "binv_server_create", "binv_submit", "binv_poll", "binv_next_done", "binv_server_stats",
@@ -37,7 +37,9 @@ EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "bin
 BINV_F_GRAPH = 4
 BINV_F_REFINE_FROM_FP64 = 8
 BINV_F_SAMPLED_CHECK = 16
+BINV_F_PIVOT = 32
 BINV_RESID_ESTIMATE = 1
+BINV_RESID_COMPENSATED = 2
 BINV_SERVER_STRICT_PRECISION = 1
 BINV_SERVER_FULL_CHECK = 2
 PHASES = ("pivot", "row", "schur", "other", "band", "small", "tail")
@@ -60,7 +62,8 @@ class _Timing(ctypes.Structure):
 
 class _Info(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_double), ("rho_steps", ctypes.c_double * 8), ("refine_steps", ctypes.c_int32),
-                ("fell_back", ctypes.c_int32), ("converged", ctypes.c_int32), ("sampled", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("converged", ctypes.c_int32), ("sampled", ctypes.c_int32),
+                ("rho_count", ctypes.c_int32)]
 
 
 class _Times(ctypes.Structure):
@@ -112,6 +115,9 @@ def load_library():
     lib.binv_residual.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_uint32, P,
                                   ctypes.POINTER(ctypes.c_double)]
     lib.binv_residual.restype = ctypes.c_int
+    lib.binv_residual_matrix.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
+                                         P, ctypes.POINTER(ctypes.c_double)]
+    lib.binv_residual_matrix.restype = ctypes.c_int
     lib.binv_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint32,
                                        ctypes.POINTER(P)]
     lib.binv_server_create.restype = ctypes.c_int
@@ -214,7 +220,7 @@ def default_context(device: int = 0) -> Context:
     return _ctx[device]
 
 
-def _opts(part=None, block=None, sync=False, lookahead=True):
+def _opts(part=None, block=None, sync=False, lookahead=True, pivot=False):
     o = _Opts()
     keep = None
     if part is not None:
@@ -226,7 +232,7 @@ def _opts(part=None, block=None, sync=False, lookahead=True):
         o.k = 0
         o.part = None
     o.block = int(block) if block else 0
-    o.flags = (BINV_F_SYNC if sync else 0) | (0 if lookahead else BINV_F_NO_LOOKAHEAD)
+    o.flags = (BINV_F_SYNC if sync else 0) | (0 if lookahead else BINV_F_NO_LOOKAHEAD) | (BINV_F_PIVOT if pivot else 0)
     return o, keep
 
 
@@ -234,7 +240,8 @@ def _stream_handle(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True):
+def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True,
+           pivot=False):
     """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
     inversion over the diagonal blocks `part` (or uniform blocks of `block`).
 
@@ -243,6 +250,8 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     sync:    wait for completion and raise SingularError on an exactly-zero pivot.
     lookahead: form the next block's pivot and panels on a side stream while
              the current trailing update runs (bitwise identical results).
+    pivot:   block-row pivoting (BINV_F_PIVOT): each pivot block's rows are
+             chosen among all rows not yet used as pivots.
     info:    optional int64 CUDA tensor of one element receiving the singular row.
     """
     import torch
@@ -264,7 +273,7 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
         X = torch.empty_like(A, memory_format=torch.contiguous_format)
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
     ctx = ctx or default_context(dev)
-    o, keep = _opts(part, block, sync, lookahead)
+    o, keep = _opts(part, block, sync, lookahead, pivot)
     info_ptr = None
     if info is not None:
         if info.dtype != torch.int64 or not info.is_cuda or info.numel() < 1:
@@ -282,7 +291,7 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
 
 
 def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=True,
-                 from_fp64=False, sampled_check=False):
+                 from_fp64=False, sampled_check=False, pivot=False):
     """Mixed-precision inversion: FP32 blockwise sweep (FP64 pivot blocks), then
     FP64 Newton-Schulz refinement to rho = ||AX - I||_F / sqrt(n) <= target.
     Synchronous.  Returns (X, info dict)."""
@@ -294,7 +303,7 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
     X = out if out is not None else torch.empty_like(A, memory_format=torch.contiguous_format)
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
     ctx = ctx or default_context(dev)
-    o, keep = _opts(part, block, False, lookahead)
+    o, keep = _opts(part, block, False, lookahead, pivot)
     if from_fp64:
         o.flags |= BINV_F_REFINE_FROM_FP64
     if sampled_check:
@@ -308,12 +317,13 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
     del keep
     _check(st)
     k = inf.refine_steps
-    return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: k + 1 + inf.fell_back]), "refine_steps": k,
+    return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: inf.rho_count]), "refine_steps": k,
                "fell_back": bool(inf.fell_back), "converged": bool(inf.converged), "sampled": inf.sampled}
 
 
-def residual(A, X, estimate=False, ctx=None):
-    """rho = ||AX - I||_F / sqrt(n) on the GPU: the full FP64 residual, or with
+def residual(A, X, estimate=False, ctx=None, compensated=False):
+    """rho = ||AX - I||_F / sqrt(n) on the GPU: the full FP64 residual (with
+    compensated=True formed through an error-free split of A and X), or with
     estimate=True its 64-probe random-sign estimate (exact below order 192)."""
     import torch
 
@@ -329,10 +339,29 @@ def residual(A, X, estimate=False, ctx=None):
     with torch.cuda.device(dev):
         st = load_library().binv_residual(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
                                           ctypes.c_void_p(X.data_ptr()), max(X.stride(0), n, 1),
-                                          BINV_RESID_ESTIMATE if estimate else 0, _stream_handle(torch, dev),
-                                          ctypes.byref(rho))
+                                          (BINV_RESID_ESTIMATE if estimate else 0)
+                                          | (BINV_RESID_COMPENSATED if compensated else 0),
+                                          _stream_handle(torch, dev), ctypes.byref(rho))
     _check(st)
     return rho.value
+
+
+def residual_matrix(A, X, ctx=None):
+    """(R, rho): the compensated residual matrix R = I - A X on the GPU."""
+    import torch
+
+    n = A.shape[0]
+    R = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or default_context(dev)
+    rho = ctypes.c_double()
+    with torch.cuda.device(dev):
+        st = load_library().binv_residual_matrix(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(A.stride(0), n, 1),
+                                                 ctypes.c_void_p(X.data_ptr()), max(X.stride(0), n, 1),
+                                                 ctypes.c_void_p(R.data_ptr()), max(n, 1), _stream_handle(torch, dev),
+                                                 ctypes.byref(rho))
+    _check(st)
+    return R, rho.value
 
 
 def batch_shape(tier, shape):

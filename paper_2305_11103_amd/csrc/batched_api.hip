@@ -136,11 +136,11 @@ binv_status bind(binv_batch* b, const double* A, double* X, int32_t* info) {
       j.leaf.row0 = o; j.leaf.info = info + i;
       binv::StepArgs& ra = j.row;
       ra.A = P; ra.lda = bs; ra.B = Win + (int64_t)o * mi; ra.ldb = mi; ra.W = R; ra.ldw = mi;
-      ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = mi; ra.K = bs; ra.o = o; ra.b = bs;
+      ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = mi; ra.K = bs; ra.o = o; ra.b = bs; ra.oc = o;
       binv::StepArgs& sa = j.schur;
       // the old column panel goes to Ct (m-major, ld = b) before the update
       sa.A = Ct; sa.lda = bs; sa.B = R; sa.ldb = mi; sa.W = Wout; sa.ldw = mi; sa.Win = Win; sa.ldwin = mi;
-      sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs;
+      sa.R = R; sa.ldr = mi; sa.M = mi; sa.N = mi; sa.K = bs; sa.o = o; sa.b = bs; sa.oc = o;
       jobs.push_back(j);
     }
     std::stable_sort(jobs.begin() + first, jobs.end(),

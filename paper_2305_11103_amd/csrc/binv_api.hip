@@ -72,8 +72,13 @@ int sub_block() {
 // leaf and saves its column panel, then block p+1's row panel.  Step 0 reads
 // the block where it lies and writes every element of P, so no copy is made.
 // The same arithmetic as sweep() on a copy; 2 k + 1 launches instead of 4 k + 1.
+// keep_q / keep_c (optional): every sub-step's leaf inverse (slot p at
+// keep_q + 4096 p, ld = its order) and saved column panel (slot p at
+// keep_c + 64 n p, ld = n) are kept there instead of in alternating buffers,
+// so that the same sub-steps can later be applied to other columns.
 binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, const double* Wpp, int64_t ldwp, double* P,
-                               const std::vector<int32_t>& part, hipStream_t s, long long* info, int64_t row0) {
+                               const std::vector<int32_t>& part, hipStream_t s, long long* info, int64_t row0,
+                               double* keep_q = nullptr, double* keep_c = nullptr) {
   const int k = (int)part.size();
   if (k < 2) return fail(BINV_E_INVALID, "fused nested sweep needs two sub-blocks or more");
   Level& L = c->lv[level];
@@ -83,26 +88,27 @@ binv_status nested_sweep_fused(binv_ctx* c, int level, int64_t n, const double* 
     if ((st = L.r[h].ensure(sizeof(double) * 64 * (size_t)n)) != BINV_OK) return st;
     if ((st = L.p[h].ensure(sizeof(double) * 64 * 64)) != BINV_OK) return st;
   }
+  auto pslot = [&](int p) { return keep_q ? keep_q + (size_t)4096 * p : (double*)L.p[p & 1].p; };
+  auto cslot = [&](int p) { return keep_c ? keep_c + (size_t)64 * n * p : (double*)L.ct[p & 1].p; };
   std::vector<int64_t> off(k + 1, 0);
   for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
-  HIP_TRY(binv::launch_leaf_inverse(Wpp, ldwp, (double*)L.p[0].p, part[0], part[0], row0, info, s));
-  HIP_TRY(binv::launch_col_save(Wpp, ldwp, n, 0, part[0], (double*)L.ct[0].p, n, s));
-  HIP_TRY(binv::launch_row_panel((double*)L.p[0].p, part[0], Wpp, ldwp, n, 0, part[0], (double*)L.r[0].p, n, s,
-                                 nullptr));
+  HIP_TRY(binv::launch_leaf_inverse(Wpp, ldwp, pslot(0), part[0], part[0], row0, info, s));
+  HIP_TRY(binv::launch_col_save(Wpp, ldwp, n, 0, part[0], cslot(0), n, s));
+  HIP_TRY(binv::launch_row_panel(pslot(0), part[0], Wpp, ldwp, n, 0, part[0], (double*)L.r[0].p, n, s, nullptr));
   for (int p = 0; p < k; ++p) {
     const int cur = p & 1;
-    const double* Ct = (const double*)L.ct[cur].p;
+    const double* Ct = cslot(p);
     const double* R = (const double*)L.r[cur].p;
     if (p + 1 == k) {
       HIP_TRY(binv::launch_schur(Ct, n, R, n, P, n, n, off[p], part[p], 0, 0, 0, s, nullptr));
       break;
     }
     binv::SchurLeafArgs a;
-    a.ct_next = (double*)L.ct[cur ^ 1].p;
+    a.ct_next = cslot(p + 1);
     a.ldc_next = n;
     a.qo = off[p + 1];
     a.qb = part[p + 1];
-    a.p_next = (double*)L.p[cur ^ 1].p;
+    a.p_next = pslot(p + 1);
     a.row0 = row0 + off[p + 1];
     a.info = info;
     const double* Win = p == 0 ? Wpp : P;
@@ -312,6 +318,250 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
   return BINV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Block-row pivoting (BINV_F_PIVOT).  Step p of the sweep becomes:
+//   1. choose the b pivot rows among rows o..n-1 from the block's saved
+//      columns Ct (k-major), strip by strip (tournament, then the strip
+//      eliminated from the block's later columns);
+//   2. gather the pivot block in pick order and sweep it with 64-wide
+//      sub-blocks, keeping every sub-step's leaf inverse and column panel;
+//   3. gather the pivot rows (all n columns) and apply those sub-steps to
+//      them: the row panel R, with the pivot block's inverse in its p columns;
+//   4. move the chosen rows to o..o+b-1 and the displaced rows to the vacated
+//      positions (rows of W, entries of Ct, the row order perm);
+//   5. the trailing update with Ct and R, as without pivoting.
+// At the end column perm[c] of X is column c of W.
+// ---------------------------------------------------------------------------
+constexpr int kPivSub = 64;
+constexpr int kPivMaxBlock = 2047;
+constexpr int64_t kPivMaxN = 32768;
+
+binv_status piv_ensure(binv_ctx* c, int64_t n, int bmax) {
+  binv::PivWork& P = c->piv;
+  const int64_t nodes = (n + binv::kTournRows - 1) / binv::kTournRows;
+  const int nsub = (bmax + kPivSub - 1) / kPivSub;
+  binv_status st;
+  struct { binv::DevBuf* d; size_t bytes; } want[] = {
+      {&P.T, sizeof(double) * (size_t)bmax * n},
+      {&P.used, sizeof(int32_t) * (size_t)n},
+      {&P.chosen, sizeof(int32_t) * (size_t)bmax},
+      {&P.lvl[0], sizeof(int32_t) * 64 * (size_t)nodes},
+      {&P.lvl[1], sizeof(int32_t) * 64 * (size_t)nodes},
+      {&P.strip, sizeof(double) * 64 * (size_t)bmax},
+      {&P.q, sizeof(double) * 64 * 64},
+      {&P.g, sizeof(double) * 64 * (size_t)bmax},
+      {&P.sel, sizeof(double) * (size_t)bmax * bmax},
+      {&P.qs, sizeof(double) * 4096 * (size_t)nsub},
+      {&P.cs, sizeof(double) * 64 * (size_t)bmax * nsub},
+      {&P.rj, sizeof(double) * 64 * (size_t)n},
+      {&P.plan, sizeof(int32_t) * (1 + 2 * (size_t)bmax)},
+      {&P.perm, sizeof(int32_t) * (size_t)n},
+  };
+  for (auto& w : want)
+    if ((st = w.d->ensure(w.bytes)) != BINV_OK) return st;
+  return BINV_OK;
+}
+
+// 1. The pivot rows of block [o, o+b) from its saved columns Ct (b x n,
+// k-major, ld n) into piv.chosen (and piv.used).
+binv_status piv_select(binv_ctx* c, int64_t n, const double* Ct, int64_t o, int b, hipStream_t s, long long* info) {
+  binv::PivWork& P = c->piv;
+  double* T = (double*)P.T.p;
+  int32_t* used = (int32_t*)P.used.p;
+  int32_t* chosen = (int32_t*)P.chosen.p;
+  HIP_TRY(binv::launch_copy2d(Ct + o, n, T + o, n, b, n - o, s));
+  HIP_TRY(binv::launch_fill_i32(used + o, n - o, 0, s));
+  for (int c0 = 0; c0 < b; c0 += kPivSub) {
+    const int w = std::min(kPivSub, b - c0);
+    int64_t nodes = (n - o + binv::kTournRows - 1) / binv::kTournRows;
+    binv::TournArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.T = T; a.ldt = n; a.o = o; a.n = n; a.c0 = c0; a.w = w;
+    a.used = used; a.in = nullptr; a.nin = 0;
+    a.out = (int32_t*)P.lvl[0].p;
+    a.chosen = chosen; a.used_w = used; a.info = info; a.row0 = o + c0;
+    a.is_leaf = 1;
+    a.is_root = nodes == 1;
+    HIP_TRY(binv::launch_tourn_level(a, nodes, s));
+    int cur = 0;
+    while (nodes > 1) {
+      const int64_t up = (nodes + binv::kTournArity - 1) / binv::kTournArity;
+      a.is_leaf = 0;
+      a.in = (const int32_t*)P.lvl[cur].p;
+      a.nin = nodes;
+      a.out = (int32_t*)P.lvl[cur ^ 1].p;
+      a.is_root = up == 1;
+      HIP_TRY(binv::launch_tourn_level(a, up, s));
+      cur ^= 1;
+      nodes = up;
+    }
+    const int rest = b - c0 - w;
+    if (rest <= 0) continue;
+    // eliminate the strip from the block's later columns of every row:
+    // T[later] -= T[strip] (Q T[picked, later]), Q the picked strip block's inverse
+    double* S = (double*)P.strip.p;
+    double* Q = (double*)P.q.p;
+    double* G = (double*)P.g.p;
+    HIP_TRY(binv::launch_gather_kmajor(T, n, c0, b - c0, chosen + c0, w, S, b - c0, s));
+    HIP_TRY(binv::launch_leaf_inverse(S, b - c0, Q, w, w, o + c0, info, s));
+    HIP_TRY(binv::launch_gemm_rows(binv::kModeRow, Q, w, S + w, b - c0, G, rest, nullptr, 0, nullptr, 0, w, rest, w,
+                                   0, 0, 0, s));
+    HIP_TRY(binv::launch_gemm_rows(binv::kModeSchur, G, rest, T + (int64_t)c0 * n + o, n, T + (int64_t)(c0 + w) * n + o,
+                                   n, T + (int64_t)(c0 + w) * n + o, n, nullptr, 0, rest, n - o, w, 0, 0, 0, s));
+  }
+  return BINV_OK;
+}
+
+// 2. The pivot block in pick order, swept with 64-wide sub-blocks into
+// piv.qs / piv.cs (a single leaf when b <= 64).
+binv_status piv_block_ops(binv_ctx* c, int64_t n, const double* Ct, int64_t o, int b, hipStream_t s,
+                          long long* info) {
+  binv::PivWork& P = c->piv;
+  double* sel = (double*)P.sel.p;
+  HIP_TRY(binv::launch_gather_kmajor(Ct, n, 0, b, (const int32_t*)P.chosen.p, b, sel, b, s));
+  if (b <= kPivSub) {
+    HIP_TRY(binv::launch_leaf_inverse(sel, b, (double*)P.qs.p, b, b, o, info, s));
+    return BINV_OK;
+  }
+  std::vector<int32_t> sub;
+  for (int off = 0; off < b; off += kPivSub) sub.push_back(std::min(kPivSub, b - off));
+  return nested_sweep_fused(c, 1, b, sel, b, sel, sub, s, info, o, (double*)P.qs.p, (double*)P.cs.p);
+}
+
+// 3. R (b x n, ld n) = the pivot rows W[chosen, :] after the pivot block's
+// sub-steps: R[:, o:o+b] = the block's inverse, elsewhere that inverse times
+// the rows, formed by the same 64-wide row operations.
+binv_status piv_row_panel(binv_ctx* c, int64_t n, const double* W, int64_t ldw, int64_t o, int b, double* R,
+                          hipStream_t s) {
+  binv::PivWork& P = c->piv;
+  const int32_t* chosen = (const int32_t*)P.chosen.p;
+  const double* qs = (const double*)P.qs.p;
+  if (b <= kPivSub) {
+    double* Y = (double*)P.T.p;  // free once the block's rows are chosen
+    HIP_TRY(binv::launch_gather_rows(W, ldw, n, chosen, b, Y, n, s));
+    HIP_TRY(binv::launch_gemm_rows(binv::kModeRow, qs, b, Y, n, R, n, nullptr, 0, qs, b, b, n, b, 0, o, b, s));
+    return BINV_OK;
+  }
+  HIP_TRY(binv::launch_gather_rows(W, ldw, n, chosen, b, R, n, s));
+  double* rj = (double*)P.rj.p;
+  for (int s0 = 0, j = 0; s0 < b; s0 += kPivSub, ++j) {
+    const int sb = std::min(kPivSub, b - s0);
+    const double* q = qs + (size_t)4096 * j;
+    const double* cj = (const double*)P.cs.p + (size_t)64 * b * j;
+    HIP_TRY(binv::launch_gemm_rows(binv::kModeRow, q, sb, R + (int64_t)s0 * n, n, rj, n, nullptr, 0, q, sb, sb, n, sb,
+                                   0, o + s0, sb, s));
+    HIP_TRY(binv::launch_gemm_rows(binv::kModeSchur, cj, b, rj, n, R, n, R, n, rj, n, b, n, sb, s0, o + s0, sb, s));
+  }
+  return BINV_OK;
+}
+
+binv_status sweep_pivoted(binv_ctx* c, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
+                          hipStream_t s, long long* info, bool lookahead) {
+  int bmax = 0;
+  for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  const int k = (int)part.size();
+  if (bmax > kPivMaxBlock || n > kPivMaxN)
+    return fail(BINV_E_INVALID, "block-row pivoting needs blocks of order <= 2047 and n <= 32768");
+  lookahead = lookahead && k >= 2;
+  Level& L = c->lv[0];
+  binv_status st;
+  for (int h = 0; h < 2; ++h) {
+    if ((st = L.ct[h].ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+    if ((st = L.r[h].ensure(sizeof(double) * (size_t)bmax * (size_t)n)) != BINV_OK) return st;
+  }
+  if ((st = piv_ensure(c, n, bmax)) != BINV_OK) return st;
+  if (lookahead && (st = ensure_side(c)) != BINV_OK) return st;
+  binv::PivWork& P = c->piv;
+  int32_t* perm = (int32_t*)P.perm.p;
+  std::vector<int64_t> off(k + 1, 0);
+  for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
+  HIP_TRY(binv::launch_iota_i32(perm, n, s));
+
+  // steps 1-4 of block p, whose columns are saved in Ct
+  auto choose_and_panel = [&](int p, double* Ct, double* R, hipStream_t sc, hipStream_t sg) -> binv_status {
+    binv_status e;
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_PIVOT, sc);
+      if ((e = piv_select(c, n, Ct, off[p], part[p], sc, info)) != BINV_OK) return e;
+      if ((e = piv_block_ops(c, n, Ct, off[p], part[p], sc, info)) != BINV_OK) return e;
+    }
+    if (sc != sg) {
+      HIP_TRY(hipEventRecord(c->ev_join, sc));
+      HIP_TRY(hipStreamWaitEvent(sg, c->ev_join, 0));
+    }
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_ROW, sg);
+      if ((e = piv_row_panel(c, n, W, ldw, off[p], part[p], R, sg)) != BINV_OK) return e;
+    }
+    PhaseTimer t(c, 0, BINV_PHASE_OTHER, sg);
+    HIP_TRY(binv::launch_moves((const int32_t*)P.used.p, (const int32_t*)P.chosen.p, off[p], part[p], n, bmax,
+                               (int32_t*)P.plan.p, perm, W, ldw, Ct, n, sg));
+    return BINV_OK;
+  };
+
+  if (!lookahead) {
+    double* Ct = (double*)L.ct[0].p;
+    double* R = (double*)L.r[0].p;
+    for (int p = 0; p < k; ++p) {
+      {
+        PhaseTimer t(c, 0, BINV_PHASE_OTHER, s);
+        HIP_TRY(binv::launch_col_save(W, ldw, n, off[p], part[p], Ct, n, s));
+      }
+      if ((st = choose_and_panel(p, Ct, R, s, s)) != BINV_OK) return st;
+      PhaseTimer t(c, 0, BINV_PHASE_SCHUR, s);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, s, t.fl(), 0));
+    }
+    PhaseTimer t(c, 0, BINV_PHASE_OTHER, s);
+    HIP_TRY(binv::launch_unpermute_cols(W, ldw, n, perm, s));
+    return BINV_OK;
+  }
+
+  // Lookahead: step p updates block q = p+1's whole column band first (every
+  // row: q's pivot rows may come from anywhere below), saving q's columns;
+  // then the rest of the trailing update on g while q's pivot rows are chosen
+  // and its block swept on the side stream; g then forms q's row panel and
+  // moves the rows.
+  {
+    PhaseTimer t(c, 0, BINV_PHASE_OTHER, s);
+    HIP_TRY(binv::launch_col_save(W, ldw, n, off[0], part[0], (double*)L.ct[0].p, n, s));
+  }
+  if ((st = choose_and_panel(0, (double*)L.ct[0].p, (double*)L.r[0].p, s, s)) != BINV_OK) return st;
+  hipStream_t g = c->gemm;
+  HIP_TRY(hipEventRecord(c->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(g, c->ev_fork, 0));
+  for (int p = 0; p < k; ++p) {
+    const int cur = p & 1;
+    double* Ct = (double*)L.ct[cur].p;
+    double* R = (double*)L.r[cur].p;
+    if (p + 1 == k) {
+      PhaseTimer t(c, 0, BINV_PHASE_SCHUR, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, g, t.fl(), 0));
+      break;
+    }
+    double* Ctq = (double*)L.ct[cur ^ 1].p;
+    const binv::ColSave cs{Ctq, n, off[p + 1], part[p + 1]};
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_BAND, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 5, off[p + 1], part[p + 1], g, t.fl(), 0,
+                                 1.0, &cs));
+    }
+    HIP_TRY(hipEventRecord(c->ev_fork, g));
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    {
+      PhaseTimer t(c, 0, BINV_PHASE_SCHUR, g);
+      HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 6, off[p + 1], part[p + 1], g, t.fl(), 0));
+    }
+    if ((st = choose_and_panel(p + 1, Ctq, (double*)L.r[cur ^ 1].p, c->side, g)) != BINV_OK) return st;
+  }
+  {
+    PhaseTimer t(c, 0, BINV_PHASE_OTHER, g);
+    HIP_TRY(binv::launch_unpermute_cols(W, ldw, n, perm, g));
+  }
+  HIP_TRY(hipEventRecord(c->ev_gemm, g));
+  HIP_TRY(hipStreamWaitEvent(s, c->ev_gemm, 0));
+  return BINV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -356,8 +606,10 @@ binv_status binv_destroy(binv_ctx* ctx) {
   for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_gemm})
     if (e) (void)hipEventDestroy(e);
   ctx->info.release();
+  ctx->piv.release();
   for (binv::DevBuf* d : {&ctx->mx_w32, &ctx->mx_ct32, &ctx->mx_r32, &ctx->mx_p32, &ctx->mx_p64a, &ctx->mx_p64b,
-                          &ctx->mx_res, &ctx->mx_xn, &ctx->mx_part})
+                          &ctx->mx_res, &ctx->mx_xn, &ctx->mx_part, &ctx->mx_split_a, &ctx->mx_split_x,
+                          &ctx->mx_exps})
     d->release();
   for (auto& p : ctx->pending) {
     (void)hipEventSynchronize(p.b);
@@ -436,10 +688,25 @@ binv_status read_info(long long* info, hipStream_t s, long long* h) {
   return BINV_OK;
 }
 
-// rho = ||I - A X||_F / sqrt(n) with the residual left in Res (FP64 GEMM).
+// rho = ||I - A X||_F / sqrt(n) with the residual left in Res.  Plain: one
+// FP64 GEMM.  Compensated: the error-free split of A and X (three FP64 GEMMs,
+// see launch_resid_compensated), accurate to about the rounding of R itself
+// rather than to u |A| |X|; A's split is reused while c->split_a_of == A.
 binv_status residual_norm(binv_ctx* c, int64_t n, const double* A, int64_t lda, const double* X, int64_t ldx,
-                          double* Res, hipStream_t s, double* rho) {
-  HIP_TRY(binv::launch_gemm_f64(binv::kModeResid, A, lda, X, ldx, nullptr, 0, Res, n, n, s, nullptr));
+                          double* Res, hipStream_t s, double* rho, bool compensated = false) {
+  if (compensated) {
+    const size_t nn = (size_t)n * (size_t)n;
+    binv_status st;
+    if ((st = c->mx_split_a.ensure(sizeof(double) * 2 * nn)) != BINV_OK) return st;
+    if ((st = c->mx_split_x.ensure(sizeof(double) * 2 * nn)) != BINV_OK) return st;
+    if ((st = c->mx_exps.ensure(sizeof(int) * 2 * (size_t)n)) != BINV_OK) return st;
+    const bool fresh = c->split_a_of != A;
+    HIP_TRY(binv::launch_resid_compensated(A, lda, X, ldx, n, Res, (double*)c->mx_split_a.p,
+                                           (double*)c->mx_split_x.p, (int*)c->mx_exps.p, fresh, s, nullptr));
+    c->split_a_of = A;
+  } else {
+    HIP_TRY(binv::launch_gemm_f64(binv::kModeResid, A, lda, X, ldx, nullptr, 0, Res, n, n, s, nullptr));
+  }
   double* part = (double*)c->mx_part.p;
   HIP_TRY(binv::launch_sumsq(Res, n, n, n, part, part + binv::kSumPartsHost, s));
   double h = 0.0;
@@ -534,7 +801,9 @@ binv_status binv_residual(binv_ctx* ctx, int64_t n, const double* A, int64_t lda
                           uint32_t flags, void* stream, double* rho) {
   if (!ctx || !rho) return fail(BINV_E_INVALID, "ctx or rho is NULL");
   if (n < 0) return fail(BINV_E_INVALID, "n < 0");
-  if (flags & ~BINV_RESID_ESTIMATE) return fail(BINV_E_INVALID, "unknown flags");
+  if (flags & ~(BINV_RESID_ESTIMATE | BINV_RESID_COMPENSATED)) return fail(BINV_E_INVALID, "unknown flags");
+  if ((flags & BINV_RESID_ESTIMATE) && (flags & BINV_RESID_COMPENSATED))
+    return fail(BINV_E_INVALID, "the estimate has no compensated form");
   *rho = 0.0;
   if (n == 0) return BINV_OK;
   if (!A || !X) return fail(BINV_E_INVALID, "A or X is NULL");
@@ -548,8 +817,37 @@ binv_status binv_residual(binv_ctx* ctx, int64_t n, const double* A, int64_t lda
   if (st == BINV_OK) st = ctx->mx_part.ensure(sizeof(double) * (binv::kSumPartsHost + 1));
   if (st == BINV_OK) {
     double* Res = (double*)ctx->mx_res.p;
+    ctx->split_a_of = nullptr;
     st = estimate ? probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho)
-                  : residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho);
+                  : residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho, (flags & BINV_RESID_COMPENSATED) != 0);
+  }
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+binv_status binv_residual_matrix(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, const double* X,
+                                 int64_t ldx, double* R, int64_t ldr, void* stream, double* rho) {
+  if (!ctx || !rho) return fail(BINV_E_INVALID, "ctx or rho is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  *rho = 0.0;
+  if (n == 0) return BINV_OK;
+  if (!A || !X || !R) return fail(BINV_E_INVALID, "A, X or R is NULL");
+  if (lda < n || ldx < n || ldr < n) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  binv_status st = ctx->mx_res.ensure(sizeof(double) * (size_t)n * (size_t)n);
+  if (st == BINV_OK) st = ctx->mx_part.ensure(sizeof(double) * (binv::kSumPartsHost + 1));
+  if (st == BINV_OK) {
+    ctx->split_a_of = nullptr;
+    double* Res = (double*)ctx->mx_res.p;
+    st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, rho, true);
+    if (st == BINV_OK) {
+      hipError_t e = binv::launch_copy2d(Res, n, R, ldr, n, n, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = fail(BINV_E_HIP, hipGetErrorString(e));
+    }
   }
   if (prev != ctx->device) (void)hipSetDevice(prev);
   return st;
@@ -597,6 +895,7 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
   if ((st = ctx->mx_res.ensure(sizeof(double) * nn)) != BINV_OK) goto out;
   if ((st = ctx->mx_xn.ensure(sizeof(double) * nn)) != BINV_OK) goto out;
   if ((st = ctx->mx_part.ensure(sizeof(double) * (binv::kSumPartsHost + 1))) != BINV_OK) goto out;
+  ctx->split_a_of = nullptr;  // A's split is formed afresh by this call
   Res = (double*)ctx->mx_res.p;
   Xn = (double*)ctx->mx_xn.p;
   {
@@ -606,12 +905,15 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
   {
     const bool look = !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD));
     const bool from64 = opts && (opts->flags & BINV_F_REFINE_FROM_FP64);
+    const bool pivot = opts && (opts->flags & BINV_F_PIVOT);
     // small orders take the full residual, which is as cheap as the estimate there
     const bool sampled = opts && (opts->flags & BINV_F_SAMPLED_CHECK) && n >= kProbeMinN;
     if (from64) {
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
-      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK) goto out;
+      if ((st = pivot ? sweep_pivoted(ctx, n, X, ldx, part, s, dinfo, look)
+                      : sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK)
+        goto out;
     } else {
       if ((st = sweep_f32(ctx, n, A, lda, X, ldx, part, s, dinfo)) != BINV_OK) goto out;
     }
@@ -623,51 +925,67 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
       if ((st = probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
       if (est <= target) {
         inf.rho_steps[0] = est;
+        inf.rho_count = 1;
         inf.rho = est;
         inf.sampled = 1;
         inf.converged = 1;
         goto out;
       }
     }
-    if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+    if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho, true)) != BINV_OK) goto out;
     if (!(rho < 0.5) && !from64) {
       // the FP32 sweep is too inaccurate for Newton-Schulz to converge: start
       // again from the FP64 sweep (and refine that)
       inf.fell_back = 1;
       inf.rho_steps[0] = rho;
+      inf.rho_count = 1;
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
-      if ((st = sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK) goto out;
+      if ((st = pivot ? sweep_pivoted(ctx, n, X, ldx, part, s, dinfo, look)
+                      : sweep(ctx, 0, n, X, ldx, part, s, dinfo, 0, look)) != BINV_OK)
+        goto out;
       if ((st = read_info(dinfo, s, &hinfo)) != BINV_OK) goto out;
       if (hinfo != 0) { st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo)); goto out; }
-      if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
+      if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho, true)) != BINV_OK) goto out;
     }
     int hk = inf.fell_back ? 1 : 0;  // next free slot of rho_steps
     if (hk < 8) inf.rho_steps[hk++] = rho;
+    inf.rho_count = hk;
     for (int k = 0; rho > target && k < max_refine && rho < 0.5; ++k) {
-      // X <- X + X (I - A X)
+      // Xn = X + X (I - A X); X takes Xn only if Xn's residual is smaller, so
+      // a step that stagnates at the rounding floor (or diverges) leaves the
+      // better iterate and its rho in place
       {
         PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
         hipError_t e = binv::launch_gemm_f64(binv::kModeAdd, X, ldx, Res, n, X, ldx, Xn, n, n, s, nullptr);
-        if (e == hipSuccess) e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
         if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
       }
-      inf.refine_steps = k + 1;
-      const double prev_rho = rho;
       if (sampled) {
         double est = 0.0;
-        if ((st = probe_residual_norm(ctx, n, A, lda, X, ldx, Res, s, &est)) != BINV_OK) goto out;
+        if ((st = probe_residual_norm(ctx, n, A, lda, Xn, n, Res, s, &est)) != BINV_OK) goto out;
         if (est <= target) {
+          hipError_t e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
+          if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+          inf.refine_steps = k + 1;
           if (hk < 8) inf.rho_steps[hk++] = est;
+          inf.rho_count = hk;
           inf.rho = est;
           inf.sampled = 1;
           inf.converged = 1;
           goto out;
         }
       }
-      if ((st = residual_norm(ctx, n, A, lda, X, ldx, Res, s, &rho)) != BINV_OK) goto out;
-      if (hk < 8) inf.rho_steps[hk++] = rho;
-      if (!(rho < prev_rho)) break;  // stagnated at the rounding floor (or diverging)
+      double rho_n = 0.0;
+      if ((st = residual_norm(ctx, n, A, lda, Xn, n, Res, s, &rho_n, true)) != BINV_OK) goto out;
+      if (hk < 8) inf.rho_steps[hk++] = rho_n;
+      inf.rho_count = hk;
+      if (!(rho_n < rho)) break;  // rejected: X and rho stay
+      {
+        hipError_t e = binv::launch_copy2d(Xn, n, X, ldx, n, n, s);
+        if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+      }
+      rho = rho_n;
+      inf.refine_steps = k + 1;
     }
     inf.converged = rho <= target;
   }
@@ -718,7 +1036,7 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     const bool look = !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2;
     // out of place with the lookahead: block 0's pivot inversion reads A and
     // runs on the side stream beside the copy of A into X
-    const bool early = look && !inplace;
+    const bool early = look && !inplace && !(flags & BINV_F_PIVOT);
     if (early) {
       if ((st = ensure_side(ctx)) != BINV_OK) goto out;
       hipError_t e = hipEventRecord(ctx->ev_fork, s);
@@ -729,7 +1047,10 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
     }
-    st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
+    if (flags & BINV_F_PIVOT)
+      st = sweep_pivoted(ctx, n, X, ldx, part, s, info, !(flags & BINV_F_NO_LOOKAHEAD));
+    else
+      st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
     if (st != BINV_OK) goto out;
   }
   if (flags & BINV_F_SYNC) {

@@ -28,8 +28,10 @@ struct StepArgs {
   int64_t ldr;
   int64_t M, N;       // output extent
   int K;              // contraction length (= b)
-  int64_t o;          // first row/column of block p
+  int64_t o;          // first row of block p
   int b;              // order of block p
+  int64_t oc;         // first column of block p (== o except where a panel of
+                      // pivot rows is updated on its own)
   // tile subset (Schur update): 0 = every tile; 1 = the band of tile-rows
   // [tr0, tr1] and tile-columns [tc0, tc1] (the next block's rows and
   // columns); 2 = every tile outside that band.
@@ -101,6 +103,7 @@ hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, i
                          hipStream_t s);
 hipError_t launch_zero_info(long long* p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64_t ldw, int64_t n, int64_t o, int b,
                             double* R, int64_t ldr, hipStream_t s, double* flops);
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
@@ -111,10 +114,51 @@ hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int
                              hipStream_t s);
 hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s);
 
+// block-row pivoting (kernels.hip): one level of the tournament that picks a
+// strip's pivot rows (see k_tourn_node)
+struct TournArgs {
+  const double* T;     // the block's columns, k-major: T[col * ldt + row], rows global
+  int64_t ldt;
+  int64_t o, n;        // candidate rows [o, n)
+  int c0, w;           // strip columns [c0, c0 + w), w <= 64
+  const int32_t* used; // used[row] != 0: chosen by an earlier strip of this block
+  const int32_t* in;   // merge levels: the children's picks (nin nodes x 64, -1 = none)
+  int64_t nin;
+  int32_t* out;        // this level's picks (nodes x 64, -1 = none)
+  int32_t* chosen;     // root: chosen[c0 + t] = pick t
+  int32_t* used_w;     // root: marks its picks in used
+  long long* info;     // root: first exactly-zero pivot, reported as row0 + c + 1
+  int64_t row0;
+  int is_leaf, is_root;
+};
+constexpr int kTournRows = 256;   // candidate rows per node (leaf rows; 4 children x 64 picks)
+constexpr int kTournArity = 4;
+hipError_t launch_tourn_level(const TournArgs& a, int64_t nodes, hipStream_t s);
+hipError_t launch_gather_kmajor(const double* T, int64_t ldt, int c0, int ncols, const int32_t* rows, int nrows,
+                                double* S, int64_t lds, hipStream_t s);
+hipError_t launch_gather_rows(const double* W, int64_t ldw, int64_t ncols, const int32_t* rows, int nrows, double* Y,
+                              int64_t ldy, hipStream_t s);
+hipError_t launch_moves(const int32_t* used, const int32_t* chosen, int64_t o, int b, int64_t n, int bmax,
+                        int32_t* plan, int32_t* perm, double* W, int64_t ldw, double* Ct, int64_t ldc,
+                        hipStream_t s);
+hipError_t launch_unpermute_cols(double* W, int64_t ldw, int64_t n, const int32_t* perm, hipStream_t s);
+hipError_t launch_gemm_rows(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, double* W,
+                            int64_t ldw, const double* Win, int64_t ldwin, const double* R, int64_t ldr, int64_t M,
+                            int64_t N, int K, int64_t o, int64_t oc, int b, hipStream_t s);
+constexpr int kModeRow = 0;    // W = A B with R in block p's columns
+constexpr int kModeSchur = 1;  // W = Win - A B with R in block p's rows
+
 hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, const double* Cin,
                            int64_t ldcin, double* C, int64_t ldc, int64_t n, hipStream_t s, double* flops);
 hipError_t launch_probe_residual(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n,
                                  double* work, uint64_t seed, double* part, int kParts, hipStream_t s);
+// R = I - A X with an error-free split of A (by rows) and X (by columns):
+// split_a and split_x hold 2 n^2 doubles each, exps 2 n ints; fresh_a = false
+// reuses split_a from an earlier call with the same A.
+hipError_t launch_resid_compensated(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n,
+                                    double* R, double* split_a, double* split_x, int* exps, bool fresh_a,
+                                    hipStream_t s, double* flops);
+int split_bits(int64_t n);
 constexpr int kModeResid = 2;  // C = I - A B
 constexpr int kModeAdd = 3;    // C = Cin + A B
 
@@ -193,6 +237,27 @@ struct Level {
   DevBuf p[2];   // pivot inverse: b x b
 };
 
+// Workspace of block-row pivoting (sized before a pivoted sweep starts).
+struct PivWork {
+  DevBuf T;       // bmax x n doubles: a block's columns, eliminated strip by strip to choose its pivot rows
+  DevBuf used;    // n int32: rows chosen by earlier strips of the block
+  DevBuf chosen;  // bmax int32: the block's pivot rows in pick order
+  DevBuf lvl[2];  // tournament picks of consecutive levels: ceil(n / 256) x 64 int32 each
+  DevBuf strip;   // 64 x bmax: the picked rows' strip and later columns
+  DevBuf q;       // 64 x 64: inverse of the picked rows' strip block
+  DevBuf g;       // 64 x bmax: that inverse times the picked rows' later columns
+  DevBuf sel;     // bmax x bmax: the pivot block in pick order (inverted in place)
+  DevBuf qs;      // (bmax / 64) x 64 x 64: the pivot block sweep's leaf inverses
+  DevBuf cs;      // (bmax / 64) x 64 x bmax: its saved column panels
+  DevBuf rj;      // 64 x n: one sub-step's row panel over the pivot rows
+  DevBuf plan;    // 1 + 2 bmax int32: the row moves
+  DevBuf perm;    // n int32: the original row at each position
+  void release() {
+    for (DevBuf* d : {&T, &used, &chosen, &lvl[0], &lvl[1], &strip, &q, &g, &sel, &qs, &cs, &rj, &plan, &perm})
+      d->release();
+  }
+};
+
 }  // namespace binv
 
 // The library context (opaque to callers; see include/binv.h).
@@ -201,6 +266,7 @@ struct binv_ctx {
   int ncu = 256;  // compute units of the device
   binv::Level lv[2];
   binv::DevBuf info;  // scratch info word when the caller passes none
+  binv::PivWork piv;  // block-row pivoting
   // lookahead: the trailing update runs on `gemm` (CU-masked to all but a few
   // CUs) while the next pivot inversion runs on `side` (masked to the rest)
   hipStream_t side = nullptr, gemm = nullptr;
@@ -212,6 +278,9 @@ struct binv_ctx {
   int8_t tuned_small[5][40];
   // mixed precision workspace
   binv::DevBuf mx_w32, mx_ct32, mx_r32, mx_p32, mx_p64a, mx_p64b, mx_res, mx_xn, mx_part;
+  // compensated residual: the split parts of A and of X, and their exponents
+  binv::DevBuf mx_split_a, mx_split_x, mx_exps;
+  const double* split_a_of = nullptr;  // the A whose split mx_split_a holds (within one call)
   // optional per-phase event timing
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t> ev_free;

@@ -282,6 +282,10 @@ __global__ void k_zero_i64(long long* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+__global__ void __launch_bounds__(256) k_iota_i32(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = (int32_t)i;
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
 }
@@ -338,6 +342,13 @@ __host__ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t 
     tm = (mi < tr0) ? mi : mi + nr;
     return true;
   }
+  if (region == 5) {  // the tile-columns [tc0, tc1], every tile-row
+    const int64_t nc = tc1 - tc0 + 1;
+    if (t >= TM * nc) return false;
+    tm = t / nc;
+    tn = tc0 + t % nc;
+    return true;
+  }
   if (region == 3) {  // the diagonal tile block [tr0, tr1] x [tc0, tc1] only
     const int64_t nc = tc1 - tc0 + 1;
     if (t >= (tr1 - tr0 + 1) * nc) return false;
@@ -355,6 +366,7 @@ __host__ __device__ __forceinline__ bool tile_of(int64_t t, int64_t TM, int64_t 
   tn = r / rows;
   if (region == 2 && ((tm >= tr0 && tm <= tr1) || (tn >= tc0 && tn <= tc1))) return false;
   if (region == 4 && tm >= tr0 && tm <= tr1 && tn >= tc0 && tn <= tc1) return false;
+  if (region == 6 && tn >= tc0 && tn <= tc1) return false;
   return true;
 }
 
@@ -469,7 +481,7 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
   } else if (MODE == MODE_SCHUR) {
     if (m0 >= o && m0 + BM <= o + b) need = false;  // rows inside block p: copy of R
   } else {
-    if (n0 >= o && n0 + BN <= o + b) need = false;  // columns inside block p: copy of P
+    if (n0 >= g.oc && n0 + BN <= g.oc + b) need = false;  // columns inside block p: copy of P
   }
 
   double acc[RG][CG];
@@ -619,14 +631,14 @@ __device__ __forceinline__ void gemm_tile(const StepArgs& g, int64_t tm, int64_t
     for (int c = 0; c < CG; ++c) {
       const int64_t j = n0 + wn * WN + c * 16 + ec;
       if (j >= g.N) continue;
-      const bool jp = (j >= o && j < o + b);
+      const bool jp = (j >= g.oc && j < g.oc + b);
       if (MODE == MODE_RESID) {
         g.W[i * g.ldw + j] = (i == j ? 1.0 : 0.0) - acc[r][c];
       } else if (MODE == MODE_ADD) {
         g.W[i * g.ldw + j] = g.Win[i * g.ldwin + j] + acc[r][c];
       } else if (MODE == MODE_ROW) {
         // R[i][j] = P[i][j - o] for the block's own columns, else (P W_p)[i][j]
-        g.W[i * g.ldw + j] = jp ? g.R[i * g.ldr + (j - o)] : acc[r][c];
+        g.W[i * g.ldw + j] = jp ? g.R[i * g.ldr + (j - g.oc)] : acc[r][c];
       } else {
         const bool ip = (i >= o && i < o + b);
         double val;
@@ -734,6 +746,13 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)(g < 1024 ? g : 1024)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_info(long long* p, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, s, p);
   return hipGetLastError();
@@ -756,7 +775,7 @@ static double step_flops(const StepArgs& g, int mode) {
     const int64_t c0 = tn * BN, c1 = (c0 + BN < g.N) ? c0 + BN : g.N;
     int64_t cols = c1 - c0;
     if (mode == MODE_ROW) {
-      const int64_t a = (c0 > g.o) ? c0 : g.o, z = (c1 < g.o + g.b) ? c1 : g.o + g.b;
+      const int64_t a = (c0 > g.oc) ? c0 : g.oc, z = (c1 < g.oc + g.b) ? c1 : g.oc + g.b;
       if (z > a) cols -= z - a;
     }
     return (double)rows * (double)cols;
@@ -791,6 +810,7 @@ static hipError_t launch_step(StepArgs g, hipStream_t s, int region, int64_t qo,
     g.tc1 = (qo + qb - 1) / BN;
     if (region == 1) T = (g.tr1 - g.tr0 + 1) * TN + (TM - (g.tr1 - g.tr0 + 1)) * (g.tc1 - g.tc0 + 1);
     if (region == 3) T = (g.tr1 - g.tr0 + 1) * (g.tc1 - g.tc0 + 1);
+    if (region == 5) T = TM * (g.tc1 - g.tc0 + 1);
   }
   g.ntiles = T;
   const int64_t T8 = (T + 7) / 8;
@@ -838,7 +858,7 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
   g.W = R; g.ldw = ldr;
   g.Win = nullptr; g.ldwin = 0;
   g.R = P; g.ldr = ldp;
-  g.M = b; g.N = n; g.K = b; g.o = o; g.b = b;
+  g.M = b; g.N = n; g.K = b; g.o = o; g.b = b; g.oc = o;
   // wide panels: 64 x 128 tiles on 8 waves (measured at n = 8192, b = 512:
   // 90 us per panel against 100 for 64 x 64, 95 for 128 x 64, 100 for 128 x 128)
   if (b >= 128 && n >= 2048) return launch_step<MODE_ROW, 64, 128, false, 2, 4>(g, s, 0, 0, 0, flops);
@@ -849,7 +869,8 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 // k-major) and the row panel R (b x n).  region 0: all tiles; 1: only the
 // tile band covering rows/columns [qo, qo+qb) of the next block; 2: the rest;
 // 3: only the tiles of the next block's diagonal block (rows and columns
-// [qo, qo+qb)); 4: every tile but those.  part 1 / 2 with `split`: the first
+// [qo, qo+qb)); 4: every tile but those; 5: the tile-columns covering the
+// next block's columns, every row; 6: every tile but those.  part 1 / 2 with `split`: the first
 // `split` / the rest of every XCD's share of the region's tiles.  cs: the
 // next block's column panel saved as its elements are updated.
 int schur_tile(int64_t n) { return n >= 2048 ? 128 : 64; }
@@ -863,7 +884,7 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   g.W = W; g.ldw = ldw;
   g.Win = W; g.ldwin = ldw;
   g.R = R; g.ldr = ldr;
-  g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
+  g.M = n; g.N = n; g.K = b; g.o = o; g.b = b; g.oc = o;
   if (region == 3) {
     // the next block's diagonal tiles of the trailing-update grid, updated
     // with 32 x 32 tiles (a 512-block gives 256 workgroups, one per CU, for
@@ -873,6 +894,15 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
     const int64_t a0 = qo / tile * tile;
     const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
     return launch_step<MODE_SCHUR, 32, 32, true>(g, s, 3, a0, (int)(a1 - a0), flops, 0, 1.0, cs);
+  }
+  if (region == 5) {
+    // the next block's whole column band (every row), before its pivot rows
+    // are chosen: 64 x 64 tiles over exactly the columns the trailing-update
+    // grid's tile-columns covering it span
+    const int64_t tile = schur_tile(n);
+    const int64_t a0 = qo / tile * tile;
+    const int64_t a1 = std::min<int64_t>(n, ((qo + qb - 1) / tile + 1) * tile);
+    return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 5, a0, (int)(a1 - a0), flops, 0, 1.0, cs);
   }
   if (schur_tile(n) == 128)
     return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, region, qo, qb, flops, part, split, cs);
@@ -897,7 +927,7 @@ hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int
   g.W = W; g.ldw = ldw;
   g.Win = Win; g.ldwin = ldwin;
   g.R = R; g.ldr = ldr;
-  g.M = n; g.N = n; g.K = b; g.o = o; g.b = b;
+  g.M = n; g.N = n; g.K = b; g.o = o; g.b = b; g.oc = o;
   const int64_t TT = (n + 63) / 64;
   const unsigned G = (unsigned)(TT * TT);  // one workgroup per tile
   const bool vec = (n % 64 == 0) && (b % 16 == 0) && ((ldc & 1) == 0) && ((ldr & 1) == 0) &&
@@ -919,7 +949,7 @@ hipError_t launch_gemm_f64(int mode, const double* A, int64_t lda, const double*
   g.W = C; g.ldw = ldc;
   g.Win = Cin; g.ldwin = ldcin;
   g.R = nullptr; g.ldr = 0;
-  g.M = n; g.N = n; g.K = (int)n; g.o = 0; g.b = 0;
+  g.M = n; g.N = n; g.K = (int)n; g.o = 0; g.b = 0; g.oc = 0;
   if (mode == MODE_RESID) return launch_step<MODE_RESID, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
   return launch_step<MODE_ADD, 128, 128, false, 4, 2>(g, s, 0, 0, 0, flops);
 }
@@ -946,7 +976,7 @@ k_skinny_splitk(const double* __restrict__ Mx, int64_t ldm, const double* __rest
   g.R = nullptr; g.ldr = 0;
   g.M = n; g.N = 64;
   g.K = (int)((n - k0 < kslice) ? n - k0 : kslice);
-  g.o = 0; g.b = 0;
+  g.o = 0; g.b = 0; g.oc = 0;
   gemm_tile<MODE_ROW, C, false, VEC>(g, t, 0, As, Bs);
 }
 
@@ -1081,6 +1111,471 @@ hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipS
   else
     hipLaunchKernelGGL((k_swept_step<2, 16, 8, TileCfg<64, 64, 4, 2>>), dim3((unsigned)count), dim3(512), 0, s, jobs);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Block-row pivoting (the pivot rows of block p chosen among all rows below).
+//
+// The paper's method assumes that every pivot block and Schur complement is
+// invertible and otherwise changes the blocking (§3); its counter-diagonal
+// partition, Eqs. (b) and (c), is Eq. (a) applied to a block-row permuted
+// matrix.  Here the rows that form each pivot block are chosen by tournament
+// selection on the block's current columns: strips of 64 columns in turn;
+// leaves of 256 consecutive rows (rows already chosen left out), each node
+// keeping the 64 rows that Gauss elimination with partial pivoting picks among
+// its candidates, four nodes merging into one, the root's picks (in pick
+// order) being the strip's pivot rows, which are then eliminated from the
+// block's later columns.  The chosen rows move to the block's position, the
+// rows they displace take the vacated positions, and a final column
+// permutation undoes the moves.
+// ---------------------------------------------------------------------------
+
+// Pivot search in one column held as x[h] (candidate lane + 64 h) by every
+// lane of a wave: the largest |value| among rows not yet picked, the lowest
+// candidate position on ties; kTournRows when every row is picked.
+template <int RPL>
+__device__ __forceinline__ int tourn_search(const double (&x)[RPL], const bool (&used)[RPL], double& pv) {
+  unsigned long long key[RPL];
+  unsigned long long kmax = 0;
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    key[h] = used[h] ? 0ULL : (unsigned long long)__double_as_longlong(fabs(x[h])) + 1ULL;
+    kmax = key[h] > kmax ? key[h] : kmax;
+  }
+  const unsigned hi = __ockl_wfred_max_u32((unsigned)(kmax >> 32));
+  const unsigned lo = __ockl_wfred_max_u32((unsigned)(kmax >> 32) == hi ? (unsigned)kmax : 0u);
+  kmax = ((unsigned long long)hi << 32) | lo;
+  pv = 0.0;
+  if (kmax == 0ULL) return 64 * RPL;
+  int r = 64 * RPL;
+#pragma unroll
+  for (int h = RPL - 1; h >= 0; --h) {
+    const unsigned long long mk = __ballot(key[h] == kmax);
+    if (mk) r = 64 * h + __ffsll((long long)mk) - 1;
+  }
+#pragma unroll
+  for (int h = 0; h < RPL; ++h)
+    if ((r >> 6) == h) pv = readlane_f64(x[h], r & 63);
+  return r;
+}
+
+// One tournament node per workgroup: 4 waves, lane l holding candidates
+// l + 64 h (h < 4), wave v holding strip columns [16 v, 16 v + 16).
+__global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
+  constexpr int RPL = kTournRows / 64, CPW = 16;
+  __shared__ int cand[kTournRows];
+  __shared__ int wcount[4];
+  __shared__ double colbuf[2][kTournRows];
+  __shared__ int s_r[2];
+  __shared__ double s_pv[2];
+  __shared__ int picks[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t node = blockIdx.x;
+
+  // candidates, in order: a leaf's rows not yet chosen, or the children's picks
+  int row = -1;
+  if (a.is_leaf) {
+    const int64_t r = a.o + node * kTournRows + tid;
+    if (r < a.n && a.used[r] == 0) row = (int)r;
+  } else {
+    const int64_t child = node * kTournArity + (tid >> 6);
+    if (child < a.nin) row = a.in[child * 64 + lane];
+  }
+  const unsigned long long mk = __ballot(row >= 0);
+  if (lane == 0) wcount[wave] = __popcll(mk);
+  __syncthreads();
+  int before = 0, nc = 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    before += (v < wave) ? wcount[v] : 0;
+    nc += wcount[v];
+  }
+  if (row >= 0) cand[before + __popcll(mk & ((1ULL << lane) - 1ULL))] = row;
+  __syncthreads();
+
+  const int w = a.w;
+  double v[RPL][CPW];
+  bool used[RPL];
+#pragma unroll
+  for (int h = 0; h < RPL; ++h) {
+    const int i = lane + 64 * h;
+    used[h] = i >= nc;
+    const int ri = used[h] ? 0 : cand[i];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = wave * CPW + j;
+      v[h][j] = (!used[h] && col < w) ? a.T[(int64_t)(a.c0 + col) * a.ldt + ri] : 0.0;
+    }
+  }
+  if (wave == 0) {
+    double x[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) x[h] = v[h][0];
+    double pv;
+    const int r = tourn_search<RPL>(x, used, pv);
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) colbuf[0][lane + 64 * h] = x[h];
+    if (lane == 0) {
+      s_r[0] = r;
+      s_pv[0] = pv;
+    }
+  }
+  int got = 0, zero = -1;
+  for (int c = 0; c < w; ++c) {
+    const int buf = c & 1;
+    __syncthreads();
+    const int r = s_r[buf];
+    if (r >= kTournRows) break;  // every candidate picked (uniform)
+    const double pv = s_pv[buf];
+    if (tid == 0) picks[c] = cand[r];
+    got = c + 1;
+    if (pv == 0.0 && zero < 0) zero = c;
+    const double q = pv != 0.0 ? 1.0 / pv : 0.0;
+    const int rl = __builtin_amdgcn_readfirstlane(r & 63);
+    const int rh = __builtin_amdgcn_readfirstlane(r >> 6);
+    double sp[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int h = 0; h < RPL; ++h)
+        if (h == rh) t = readlane_f64(v[h][j], rl);
+      sp[j] = t;
+    }
+    double f[RPL];
+#pragma unroll
+    for (int h = 0; h < RPL; ++h) {
+      const int i = lane + 64 * h;
+      const bool isr = (i == r);
+      f[h] = (used[h] || isr) ? 0.0 : colbuf[buf][i] * q;
+      used[h] = used[h] || isr;
+    }
+    // column c + 1 first, then its search, then the rest of the update
+    const int cn = c + 1;
+    const bool nowner = (cn < w) && (cn / CPW == wave);
+    const int jn = cn % CPW;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+      if (j == jn && nowner)
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
+    if (nowner) {
+      double x[RPL];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        x[h] = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+          if (j == jn) x[h] = v[h][j];
+      }
+      double pv2;
+      const int r2 = tourn_search<RPL>(x, used, pv2);
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) colbuf[buf ^ 1][lane + 64 * h] = x[h];
+      if (lane == 0) {
+        s_r[buf ^ 1] = r2;
+        s_pv[buf ^ 1] = pv2;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int col = wave * CPW + j;
+      if (col > c && !(j == jn && nowner))
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int pk = tid < got ? picks[tid] : -1;
+    a.out[node * 64 + tid] = pk;
+    if (a.is_root && tid < w) {
+      a.chosen[a.c0 + tid] = pk;
+      if (pk >= 0) a.used_w[pk] = 1;
+    }
+  }
+  if (a.is_root && tid == 0 && (zero >= 0 || got < w)) record_singular(a.info, a.row0 + (zero >= 0 ? zero : got) + 1);
+}
+
+// S[k][t] = T[(c0 + t) ldt + rows[k]] for k < nrows, t < ncols (rows of a
+// k-major panel gathered into a row-major block).
+__global__ void __launch_bounds__(256) k_gather_kmajor(const double* __restrict__ T, int64_t ldt, int c0, int ncols,
+                                                       const int32_t* __restrict__ rows, int nrows,
+                                                       double* __restrict__ S, int64_t lds) {
+  const int k = blockIdx.y;
+  if (k >= nrows) return;
+  const int64_t r = rows[k];
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < ncols; t += gridDim.x * 256)
+    S[(int64_t)k * lds + t] = r >= 0 ? T[(int64_t)(c0 + t) * ldt + r] : 0.0;
+}
+
+// Y[k][:] = W[rows[k]][:] (whole rows gathered).
+__global__ void __launch_bounds__(256) k_gather_rows(const double* __restrict__ W, int64_t ldw, int64_t ncols,
+                                                     const int32_t* __restrict__ rows, double* __restrict__ Y,
+                                                     int64_t ldy) {
+  const int k = blockIdx.y;
+  const int64_t r = rows[k];
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < ncols; j += (int64_t)gridDim.x * 256)
+    Y[(int64_t)k * ldy + j] = r >= 0 ? W[r * ldw + j] : 0.0;
+}
+
+// The moves of block [o, o + b) once its pivot rows chosen[0..b) are known:
+// D = the rows of [o, o + b) not chosen, V = the chosen rows at or after
+// o + b, both ascending (|D| = |V| = m); row D_i moves to V_i and the chosen
+// row chosen[k] to o + k.  One workgroup of 1024 threads: plan[0] = m,
+// plan[1 + i] = D_i, plan[1 + bmax + i] = V_i; perm (the original row at each
+// position) is updated to match.
+__global__ void __launch_bounds__(1024) k_plan_moves(const int32_t* __restrict__ used,
+                                                     const int32_t* __restrict__ chosen, int64_t o, int b,
+                                                     int64_t n, int bmax, int32_t* __restrict__ plan,
+                                                     int32_t* __restrict__ perm) {
+  __shared__ int wsum[16];
+  __shared__ int s_base;
+  __shared__ int32_t pv_chosen[2048];
+  __shared__ int32_t pv_disp[2048];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int32_t* D = plan + 1;
+  int32_t* V = plan + 1 + bmax;
+  // ordered compaction of the rows of [lo, hi) whose used flag equals want
+  auto compact = [&](int64_t lo, int64_t hi, int want, int32_t* dst) -> int {
+    __syncthreads();  // every thread has read the previous call's count
+    if (tid == 0) s_base = 0;
+    __syncthreads();
+    for (int64_t r0 = lo; r0 < hi; r0 += 1024) {
+      const int64_t r = r0 + tid;
+      const bool ok = r < hi && (used[r] != 0) == (want != 0);
+      const unsigned long long mk = __ballot(ok);
+      if (lane == 0) wsum[wave] = __popcll(mk);
+      __syncthreads();
+      int before = 0, tot = 0;
+      for (int v = 0; v < 16; ++v) {
+        before += (v < wave) ? wsum[v] : 0;
+        tot += wsum[v];
+      }
+      const int base = s_base;
+      const int at = base + before + __popcll(mk & ((1ULL << lane) - 1ULL));
+      if (ok && at < b) dst[at] = (int32_t)r;  // at most b rows qualify when the picks are consistent
+      __syncthreads();
+      if (tid == 0) s_base = base + tot;
+      __syncthreads();
+    }
+    return s_base;
+  };
+  const int m1 = compact(o, o + b, 0, D);
+  const int m2 = compact(o + b, n, 1, V);
+  const int m = m1 < m2 ? m1 : m2;  // equal unless a pick was missing
+  if (tid == 0) plan[0] = m;
+  for (int k = tid; k < b; k += 1024) pv_chosen[k] = chosen[k] >= 0 ? perm[chosen[k]] : -1;
+  for (int i = tid; i < m; i += 1024) pv_disp[i] = perm[D[i]];
+  __syncthreads();
+  for (int k = tid; k < b; k += 1024)
+    if (pv_chosen[k] >= 0) perm[o + k] = pv_chosen[k];
+  for (int i = tid; i < m; i += 1024) perm[V[i]] = pv_disp[i];
+}
+
+// Row D_i of W moves to row V_i (all n columns), and so does its entry in
+// every row of the saved column panel Ct (b x n, k-major).
+__global__ void __launch_bounds__(256) k_apply_moves(const int32_t* __restrict__ plan, int bmax, double* W,
+                                                     int64_t ldw, int64_t n, double* Ct, int64_t ldc, int b) {
+  const int i = blockIdx.y;
+  if (i >= plan[0]) return;
+  const int64_t d = plan[1 + i], v = plan[1 + bmax + i];
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+    W[v * ldw + j] = W[d * ldw + j];
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < b; t += gridDim.x * 256)
+    Ct[(int64_t)t * ldc + v] = Ct[(int64_t)t * ldc + d];
+}
+
+// X[i][perm[c]] = W[i][c] in place, one workgroup per row: every value of the
+// row is read into registers before any is written.
+template <int VPT>
+__global__ void __launch_bounds__(1024) k_unpermute_cols(double* W, int64_t ldw, int64_t n,
+                                                         const int32_t* __restrict__ perm) {
+  const int64_t i = blockIdx.x;
+  double v[VPT];
+  int32_t dst[VPT];
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int64_t c = threadIdx.x + 1024 * u;
+    const int32_t d = c < n ? perm[c] : -1;
+    dst[u] = d < n ? d : -1;
+    v[u] = c < n ? W[i * ldw + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < VPT; ++u)
+    if (dst[u] >= 0) W[i * ldw + dst[u]] = v[u];
+}
+
+// ---- launchers ----
+hipError_t launch_tourn_level(const TournArgs& a, int64_t nodes, hipStream_t s) {
+  if (nodes <= 0 || a.w <= 0 || a.w > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tourn_node, dim3((unsigned)nodes), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_kmajor(const double* T, int64_t ldt, int c0, int ncols, const int32_t* rows, int nrows,
+                                double* S, int64_t lds, hipStream_t s) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min(8, (ncols + 255) / 256);
+  hipLaunchKernelGGL(k_gather_kmajor, dim3(gx, (unsigned)nrows), dim3(256), 0, s, T, ldt, c0, ncols, rows, nrows, S,
+                     lds);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double* W, int64_t ldw, int64_t ncols, const int32_t* rows, int nrows, double* Y,
+                              int64_t ldy, hipStream_t s) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  const unsigned gx = (unsigned)std::min<int64_t>(16, (ncols + 255) / 256);
+  hipLaunchKernelGGL(k_gather_rows, dim3(gx, (unsigned)nrows), dim3(256), 0, s, W, ldw, ncols, rows, Y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_moves(const int32_t* used, const int32_t* chosen, int64_t o, int b, int64_t n, int bmax,
+                        int32_t* plan, int32_t* perm, double* W, int64_t ldw, double* Ct, int64_t ldc,
+                        hipStream_t s) {
+  if (b <= 0) return hipSuccess;
+  if (b > 2048 || bmax < b) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plan_moves, dim3(1), dim3(1024), 0, s, used, chosen, o, b, n, bmax, plan, perm);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gx = (unsigned)std::min<int64_t>(16, (n + 255) / 256);
+  hipLaunchKernelGGL(k_apply_moves, dim3(gx, (unsigned)b), dim3(256), 0, s, plan, bmax, W, ldw, n, Ct, ldc, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpermute_cols(double* W, int64_t ldw, int64_t n, const int32_t* perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n <= 8192)
+    hipLaunchKernelGGL(k_unpermute_cols<8>, dim3((unsigned)n), dim3(1024), 0, s, W, ldw, n, perm);
+  else if (n <= 16384)
+    hipLaunchKernelGGL(k_unpermute_cols<16>, dim3((unsigned)n), dim3(1024), 0, s, W, ldw, n, perm);
+  else if (n <= 32768)
+    hipLaunchKernelGGL(k_unpermute_cols<32>, dim3((unsigned)n), dim3(1024), 0, s, W, ldw, n, perm);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// General step GEMMs on 64 x 64 tiles, for panels the sweep does not cover:
+// MODE_ROW: W = A B (A m-major), with W[:, oc:oc+b] = R (b columns);
+// MODE_SCHUR: W = Win - A B (A k-major), rows [o, o+b) taking R and columns
+// [oc, oc+b) starting from zero.  b = 0 disables both special cases.
+hipError_t launch_gemm_rows(int mode, const double* A, int64_t lda, const double* B, int64_t ldb, double* W,
+                            int64_t ldw, const double* Win, int64_t ldwin, const double* R, int64_t ldr, int64_t M,
+                            int64_t N, int K, int64_t o, int64_t oc, int b, hipStream_t s) {
+  StepArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda;
+  g.B = B; g.ldb = ldb;
+  g.W = W; g.ldw = ldw;
+  g.Win = Win; g.ldwin = ldwin;
+  g.R = R; g.ldr = ldr;
+  g.M = M; g.N = N; g.K = K; g.o = o; g.b = b; g.oc = oc;
+  if (mode == MODE_ROW) return launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, nullptr);
+  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 0, 0, 0, nullptr);
+}
+
+
+// ---------------------------------------------------------------------------
+// Compensated residual R = I - A X by an error-free split of the operands
+// (Ozaki, Ogita, Oishi and Rump, 2012): A = A1 + A2 row by row and
+// X = X1 + X2 column by column, where A1 keeps `bits` bits of each row's
+// largest magnitude and X1 likewise per column.  With 2 bits + ceil(log2 n)
+// <= 52 every product of A1 X1 and every partial sum of a row-by-column dot
+// product lies on one grid of at most 53 bits, so the FP64 product A1 X1 is
+// exact whatever the summation order, and so is I - A1 X1.  Then
+// R = (I - A1 X1) - A2 X1 - A X2, where the last two terms are about 2^-bits
+// of |A||X| and their rounding errors 2^-bits times smaller than that of a
+// plain FP64 residual.
+// ---------------------------------------------------------------------------
+
+// exps[i] = the binary exponent E with max_k |M[i][k]| < 2^E (0 for a zero row).
+__global__ void __launch_bounds__(256) k_row_exponent(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                      int* __restrict__ exps) {
+  __shared__ double red[256];
+  const int64_t i = blockIdx.x;
+  double m = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) m = fmax(m, fabs(M[i * ldm + k]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int e = 0;
+    (void)frexp(red[0], &e);
+    exps[i] = e;
+  }
+}
+
+// exps[j] = the binary exponent F with max_k |M[k][j]| < 2^F, one thread per column.
+__global__ void __launch_bounds__(256) k_col_exponent(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                      int* __restrict__ exps) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double m = 0.0;
+  for (int64_t k = 0; k < n; ++k) m = fmax(m, fabs(M[k * ldm + j]));
+  int e = 0;
+  (void)frexp(m, &e);
+  exps[j] = e;
+}
+
+// Hi = M rounded to `bits` bits below 2^exp (exp of the row when by_row, of
+// the column otherwise), NegLo = Hi - M (exact): both n x n, ld n.
+__global__ void __launch_bounds__(256) k_split(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                               const int* __restrict__ exps, int by_row, int bits,
+                                               double* __restrict__ Hi, double* __restrict__ NegLo) {
+  const int64_t i = blockIdx.y;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const int e = by_row ? exps[i] : exps[j];
+    const double x = M[i * ldm + j];
+    const double h = ldexp(rint(ldexp(x, bits - e)), e - bits);
+    Hi[i * n + j] = h;
+    NegLo[i * n + j] = h - x;
+  }
+}
+
+hipError_t launch_split(const double* M, int64_t ldm, int64_t n, int by_row, int bits, int* exps, double* Hi,
+                        double* NegLo, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (by_row)
+    hipLaunchKernelGGL(k_row_exponent, dim3((unsigned)n), dim3(256), 0, s, M, ldm, n, exps);
+  else
+    hipLaunchKernelGGL(k_col_exponent, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, ldm, n, exps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned gx = (unsigned)std::min<int64_t>(64, (n + 255) / 256);
+  hipLaunchKernelGGL(k_split, dim3(gx, (unsigned)n), dim3(256), 0, s, M, ldm, n, exps, by_row, bits, Hi, NegLo);
+  return hipGetLastError();
+}
+
+// Bits kept per part so that two parts' products summed over n terms stay on
+// a 53-bit grid: 2 bits + ceil(log2 n) <= 52.
+int split_bits(int64_t n) {
+  int lg = 0;
+  while ((int64_t(1) << lg) < n) ++lg;
+  return (52 - lg) / 2;
+}
+
+// R (n x n, ld n) = I - A X, compensated: split A by rows into A1 and -A2
+// (split_a = {A1, -A2}, computed when fresh_a), X by columns into X1 and -X2
+// (split_x), then R = I - A1 X1 (exact), R += (-A2) X1, R += A (-X2).
+hipError_t launch_resid_compensated(const double* A, int64_t lda, const double* X, int64_t ldx, int64_t n,
+                                    double* R, double* split_a, double* split_x, int* exps, bool fresh_a,
+                                    hipStream_t s, double* flops) {
+  const int bits = split_bits(n);
+  const size_t nn = (size_t)n * (size_t)n;
+  hipError_t e = hipSuccess;
+  if (fresh_a) e = launch_split(A, lda, n, 1, bits, exps, split_a, split_a + nn, s);
+  if (e == hipSuccess) e = launch_split(X, ldx, n, 0, bits, exps + n, split_x, split_x + nn, s);
+  if (e == hipSuccess) e = launch_gemm_f64(MODE_RESID, split_a, n, split_x, n, nullptr, 0, R, n, n, s, nullptr);
+  if (e == hipSuccess) e = launch_gemm_f64(MODE_ADD, split_a + nn, n, split_x, n, R, n, R, n, n, s, nullptr);
+  if (e == hipSuccess) e = launch_gemm_f64(MODE_ADD, A, lda, split_x + nn, n, R, n, R, n, n, s, nullptr);
+  if (flops) *flops = 3 * 2.0 * (double)n * (double)n * (double)n;
+  return e;
 }
 
 
