@@ -50,9 +50,13 @@ extern "C" {
 
 typedef enum {
   BINV_OK = 0,
-  BINV_E_INVALID = 1,   /* bad argument (sizes, partition, pointers) */
+  BINV_E_INVALID = 1,   /* bad argument (sizes, partition, pointers), or an
+                           input matrix holding a NaN or an infinity */
   BINV_E_SINGULAR = 2,  /* an exactly-zero pivot inside a diagonal block */
   BINV_E_NOMEM = 3,     /* device allocation failed */
+  BINV_E_NOCONVERGE = 4, /* binv_invert_mixed / binv_poll: the result misses its
+                           residual target after the allowed refinement (X
+                           still holds the best iterate, info says how close) */
   BINV_E_HIP = 5,       /* a HIP runtime call failed */
   BINV_E_BUSY = 6,      /* binv_poll: the request is not finished yet */
   BINV_E_NOTFOUND = 7   /* binv_poll: unknown (or already collected) ticket */
@@ -127,10 +131,12 @@ binv_status binv_destroy(binv_ctx* ctx);
  * (leading dimension ldx).  X == A with ldx == lda inverts in place
  * (§4.2); otherwise A is left unchanged (§4.1's out-of-place form).
  *
- * d_info: optional device pointer to one int64 the call sets to 0, or to the
+ * d_info: optional device pointer to one int64 the call sets to 0, to the
  *         1-based global row of the first pivot (in block order) that was
- *         exactly zero; X is then undefined.  With BINV_F_SYNC the status is
- *         BINV_E_SINGULAR in that case.
+ *         exactly zero, or to -1 when A holds a NaN or an infinity (checked
+ *         as A is copied into X, or in a pass of its own in place); X is then
+ *         undefined.  With BINV_F_SYNC the status is BINV_E_SINGULAR or
+ *         BINV_E_INVALID in those cases.
  * opts:   may be NULL (uniform blocks of 512, asynchronous).
  * Errors: BINV_E_INVALID for n < 0, ld < n, a partition that does not sum to
  *         n or has a non-positive order, NULL matrices with n > 0, or
@@ -203,9 +209,10 @@ binv_status binv_residual_matrix(binv_ctx* ctx, int64_t n, const double* A, int6
  * never pivots across diagonal blocks, its error can grow on nonsymmetric
  * inputs; the refinement repairs that whenever the start has rho < 0.5.
  * The call is synchronous: it reads each residual norm back to decide the
- * next step, and fills *info (may be NULL).  Returns BINV_E_SINGULAR for an
- * exactly-zero pivot; a result that misses the target is not an error (see
- * info->converged). */
+ * next step, and fills *info (may be NULL).  Returns BINV_E_INVALID when A
+ * holds a NaN or an infinity, BINV_E_SINGULAR for an exactly-zero pivot, and
+ * BINV_E_NOCONVERGE when the result misses the target (X then holds the
+ * iterate with the smallest rho, reported in info->rho). */
 binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
                               const binv_opts* opts, double target, int32_t max_refine, void* stream,
                               binv_info* info);
@@ -303,6 +310,8 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * residual and refined by up to three Newton-Schulz steps where they miss
  * their target (info->sampled = 0).
  * binv_poll returns BINV_E_BUSY until the request is done; then it copies X
+ * (also when the status is BINV_E_NOCONVERGE: the request missed its target
+ * and X is its best iterate)
  * (n x n row-major, host or device pointer, may be NULL), fills *info and
  * *times (either may be NULL), releases the request's device memory and
  * forgets the ticket.  A finished request keeps its memory until it is

@@ -18,6 +18,7 @@ BINV_OK = 0
 BINV_E_INVALID = 1
 BINV_E_SINGULAR = 2
 BINV_E_NOMEM = 3
+BINV_E_NOCONVERGE = 4
 BINV_E_HIP = 5
 BINV_E_BUSY = 6
 BINV_E_NOTFOUND = 7
@@ -157,6 +158,11 @@ def load_library():
     return lib
 
 
+def last_error() -> str:
+    """The library's thread-local message for the last non-OK status."""
+    return load_library().binv_last_error().decode(errors="replace")
+
+
 def _check(status: int):
     if status == BINV_OK:
         return
@@ -281,10 +287,10 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
         info_ptr = ctypes.c_void_p(info.data_ptr())
     lda = A.stride(0) if n > 0 else 1
     ldx = X.stride(0) if n > 0 else 1
+    lib = load_library()
     with torch.cuda.device(dev):
-        st = load_library().binv_invert(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(lda, n),
-                                        ctypes.c_void_p(X.data_ptr()), max(ldx, n), ctypes.byref(o),
-                                        _stream_handle(torch, dev), info_ptr)
+        st = lib.binv_invert(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(lda, n), ctypes.c_void_p(X.data_ptr()),
+                max(ldx, n), ctypes.byref(o), _stream_handle(torch, dev), info_ptr)
     del keep
     _check(st)
     return X
@@ -315,7 +321,8 @@ def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5,
                                               float(target), int(max_refine), _stream_handle(torch, dev),
                                               ctypes.byref(inf))
     del keep
-    _check(st)
+    if st != BINV_E_NOCONVERGE:  # a missed target returns the best iterate (info["converged"] is False)
+        _check(st)
     k = inf.refine_steps
     return X, {"rho": inf.rho, "rho_steps": list(inf.rho_steps[: inf.rho_count]), "refine_steps": k,
                "fell_back": bool(inf.fell_back), "converged": bool(inf.converged), "sampled": inf.sampled}
@@ -530,7 +537,8 @@ class Server:
         if st == BINV_E_BUSY:
             return None
         del self._shapes[ticket]
-        _check(st)
+        if st != BINV_E_NOCONVERGE:  # a missed target still delivers X (info["converged"] is False)
+            _check(st)
         info = {"rho": inf.rho, "refine_steps": inf.refine_steps, "fell_back": bool(inf.fell_back),
                 "converged": bool(inf.converged), "sampled": inf.sampled}
         return X, info, {"queue_ms": tm.queue_ms, "total_ms": tm.total_ms}

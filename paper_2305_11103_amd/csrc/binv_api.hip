@@ -908,6 +908,13 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     const bool pivot = opts && (opts->flags & BINV_F_PIVOT);
     // small orders take the full residual, which is as cheap as the estimate there
     const bool sampled = opts && (opts->flags & BINV_F_SAMPLED_CHECK) && n >= kProbeMinN;
+    {
+      hipError_t e = binv::launch_copy2d_check(A, lda, const_cast<double*>(A), lda, n, n, dinfo, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(&hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+      if (hinfo < 0) { st = fail(BINV_E_INVALID, "A holds a NaN or an infinity"); goto out; }
+    }
     if (from64) {
       hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
@@ -988,6 +995,12 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
       inf.refine_steps = k + 1;
     }
     inf.converged = rho <= target;
+    if (!inf.converged) {
+      char msg[160];
+      snprintf(msg, sizeof(msg), "rho %.3e above the target %.3e after %d Newton-Schulz steps", rho, target,
+               inf.refine_steps);
+      st = fail(BINV_E_NOCONVERGE, msg);
+    }
   }
   inf.rho = rho;
 out:
@@ -1042,9 +1055,10 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
       hipError_t e = hipEventRecord(ctx->ev_fork, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("fork: ") + hipGetErrorString(e)); goto out; }
     }
-    if (!inplace) {
+    {
+      // the copy of A into X (out of place), checking that A is finite
       PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
-      hipError_t e = binv::launch_copy2d(A, lda, X, ldx, n, n, s);
+      hipError_t e = binv::launch_copy2d_check(A, lda, X, ldx, n, n, info, s);
       if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
     }
     if (flags & BINV_F_PIVOT)
@@ -1058,7 +1072,8 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     hipError_t e = hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("sync: ") + hipGetErrorString(e)); goto out; }
-    if (h != 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
+    if (h < 0) st = fail(BINV_E_INVALID, "A holds a NaN or an infinity");
+    if (h > 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
   }
 out:
   if (prev != ctx->device) (void)hipSetDevice(prev);

@@ -101,6 +101,10 @@ hipError_t launch_col_save(const double* W, int64_t ldw, int64_t n, int64_t o, i
                            hipStream_t s);
 hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
                          hipStream_t s);
+// The copy (S != D) or, in place (S == D), only the check: *info = -1 if any
+// element of S is a NaN or an infinity.
+hipError_t launch_copy2d_check(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
+                               long long* info, hipStream_t s);
 hipError_t launch_zero_info(long long* p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_iota_i32(int32_t* p, int64_t n, hipStream_t s);

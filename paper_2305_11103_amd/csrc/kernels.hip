@@ -278,6 +278,34 @@ __global__ void __launch_bounds__(256) k_copy2d(const double* __restrict__ S, in
     D[i * ldd + j] = S[i * lds + j];
 }
 
+// Copy that also checks the input: any NaN or infinity sets *info to -1
+// (unconditionally, so it wins over a singular row recorded by a pivot search
+// that read the same input).
+__global__ void __launch_bounds__(256) k_copy2d_check(const double* __restrict__ S, int64_t lds,
+                                                      double* __restrict__ D, int64_t ldd, int64_t rows,
+                                                      int64_t cols, long long* info) {
+  const int64_t i = blockIdx.y;
+  if (i >= rows) return;
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < cols; j += (int64_t)gridDim.x * 256) {
+    const double v = S[i * lds + j];
+    bad |= !isfinite(v);
+    D[i * ldd + j] = v;
+  }
+  if (bad) atomicExch((unsigned long long*)info, (unsigned long long)-1LL);
+}
+
+// The check alone (in-place calls).
+__global__ void __launch_bounds__(256) k_check_finite(const double* __restrict__ S, int64_t lds, int64_t rows,
+                                                      int64_t cols, long long* info) {
+  const int64_t i = blockIdx.y;
+  if (i >= rows) return;
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < cols; j += (int64_t)gridDim.x * 256)
+    bad |= !isfinite(S[i * lds + j]);
+  if (bad) atomicExch((unsigned long long*)info, (unsigned long long)-1LL);
+}
+
 __global__ void k_zero_i64(long long* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -736,6 +764,20 @@ hipError_t launch_copy2d(const double* S, int64_t lds, double* D, int64_t ldd, i
   if (gx > 64) gx = 64;
   dim3 grid(gx, (unsigned)rows);
   hipLaunchKernelGGL(k_copy2d, grid, dim3(256), 0, s, S, lds, D, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d_check(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
+                               long long* info, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  unsigned gx = (unsigned)((cols + 255) / 256);
+  if (gx > 64) gx = 64;
+  dim3 grid(gx, (unsigned)rows);
+  if (S == D && lds == ldd) {
+    hipLaunchKernelGGL(k_check_finite, grid, dim3(256), 0, s, S, lds, rows, cols, info);
+  } else {
+    hipLaunchKernelGGL(k_copy2d_check, grid, dim3(256), 0, s, S, lds, D, ldd, rows, cols, info);
+  }
   return hipGetLastError();
 }
 

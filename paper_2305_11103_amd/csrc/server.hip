@@ -355,6 +355,8 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
     if (e != BINV_OK) finish(s, reqs[i], e, err);
     else if (hinfo[i] != 0)
       finish(s, reqs[i], BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo[i]));
+    else if (!reqs[i]->info.converged)
+      finish(s, reqs[i], BINV_E_NOCONVERGE, "rho " + std::to_string(hrho[i]) + " above the request's target");
     else finish(s, reqs[i], BINV_OK, "");
   }
 }
@@ -420,6 +422,9 @@ void worker_main(binv_server* s, int w) {
     e = binv_invert_mixed(s->wctx[w], r->n, r->dA, r->n, r->dX, r->n, &o, kCheckMargin * r->target, -1, st,
                           &r->info);
     r->info.converged = r->info.rho <= r->target;
+    // the check asked for a margin below the target; only a result above the
+    // request's own target is reported as not converged
+    if (e == BINV_E_NOCONVERGE && r->info.converged) e = BINV_OK;
     r->fp32_start = fp32_start;
     finish(s, r, e, e == BINV_OK ? "" : binv_last_error());
   }
@@ -553,12 +558,11 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
     s->all.erase(it);
   }
   binv_status st = r->status;
-  if (st == BINV_OK && X) {
+  if (st != BINV_OK) binv::set_error(r->error);
+  if ((st == BINV_OK || st == BINV_E_NOCONVERGE) && X) {
     const size_t nn = (size_t)r->n * (size_t)r->n;
     hipError_t e = copy_sync(s, X, r->dX, sizeof(double) * nn, x_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
     if (e != hipSuccess) st = sfail(BINV_E_HIP, std::string("copy of X: ") + hipGetErrorString(e));
-  } else if (st != BINV_OK) {
-    binv::set_error(r->error);
   }
   if (info) *info = r->info;
   if (times) {

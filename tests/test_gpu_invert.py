@@ -268,3 +268,37 @@ def test_full_size_bench_configuration(gpu):
     # the inverse of a symmetric matrix is symmetric: rounding-level asymmetry only
     asym = np.max(np.abs(Xn[rows][:, rows] - Xn[rows][:, rows].T)) / np.max(np.abs(Xn))
     assert asym <= 1e-9
+
+
+@pytest.mark.parametrize("inplace,where", [(False, (0, 0)), (False, (699, 3)), (True, (5, 698)), (True, (699, 699))])
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_non_finite_input_is_invalid(gpu, inplace, where, bad):
+    """A NaN or an infinity anywhere in A: d_info = -1 and, synchronously,
+    BINV_E_INVALID (in place and out of place, with and without lookahead)."""
+    import torch
+    from paper_2305_11103_amd import binv
+    A_np = wl.diag_dominant(700, wl.stream_seed(1, 77))
+    A_np[where] = bad
+    for look in (True, False):
+        A = torch.from_numpy(A_np).cuda()
+        info = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+        binv.invert(A, part=[256, 256, 188], inplace=inplace, sync=False, info=info, lookahead=look)
+        torch.cuda.synchronize()
+        assert int(info.item()) == -1
+        A = torch.from_numpy(A_np).cuda()
+        with pytest.raises(binv.BinvError) as e:
+            binv.invert(A, part=[256, 256, 188], inplace=inplace, lookahead=look)
+        assert e.value.status == binv.BINV_E_INVALID and not isinstance(e.value, binv.SingularError)
+
+
+def test_non_finite_with_a_zero_pivot_reports_invalid(gpu):
+    """Both a NaN and an exactly-zero pivot column: the non-finite input wins."""
+    import torch
+    from paper_2305_11103_amd import binv
+    A_np = wl.diag_dominant(256, wl.stream_seed(1, 78))
+    A_np[:, 3] = 0.0
+    A_np[200, 200] = np.nan
+    info = torch.zeros(1, dtype=torch.int64, device="cuda")
+    binv.invert(torch.from_numpy(A_np).cuda(), part=[64] * 4, sync=False, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == -1

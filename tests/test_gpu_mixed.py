@@ -13,6 +13,7 @@ import oracle
 from paper_2305_11103_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
 
 
 def run(A_np, **kw):
@@ -39,8 +40,8 @@ def test_mixed_converges_to_target(gpu, n, cond, blk):
     r = info["rho_steps"][1:] if info["fell_back"] else info["rho_steps"]
     for a, b in zip(r, r[1:]):
         assert b <= 10 * np.sqrt(n) * a * a + 1e-13
-    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
-    assert err <= 1e-14 * cond * 100
+    # elementwise against Gauss-Jordan with partial pivoting (exact cond)
+    assert np.max(np.abs(X - Xo)) <= 64 * n * 2.0 ** -53 * cond * np.max(np.abs(Xo))
 
 
 def test_refinement_from_fp64_repairs_nonsymmetric_growth(gpu):
@@ -133,3 +134,40 @@ def test_mixed_degenerate_orders(gpu):
     assert X.shape == (0, 0) and info["converged"]
     X1, info1 = binv.invert_mixed(torch.tensor([[4.0]], dtype=torch.float64, device="cuda"))
     assert float(X1[0, 0]) == 0.25 and info1["converged"]
+
+
+def test_missed_target_is_noconverge_with_the_best_iterate(gpu):
+    """No refinement allowed on a start above the target: BINV_E_NOCONVERGE
+    through the C ABI, X the FP64 sweep's own result and info->converged 0."""
+    import ctypes
+    import torch
+    from paper_2305_11103_amd import binv
+    n = 768
+    A = torch.from_numpy(wl.general_haar(n, 31 + n, 1e4)).cuda()
+    X = torch.empty_like(A)
+    lib = binv.load_library()
+    o, keep = binv._opts(None, 256, False, True, False)
+    o.flags |= binv.BINV_F_REFINE_FROM_FP64
+    inf = binv._Info()
+    st = lib.binv_invert_mixed(binv.default_context(0).handle, n, ctypes.c_void_p(A.data_ptr()), n,
+                               ctypes.c_void_p(X.data_ptr()), n, ctypes.byref(o), 1e-10, 0,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(inf))
+    torch.cuda.synchronize()
+    assert st == binv.BINV_E_NOCONVERGE and "above the target" in binv.last_error()
+    assert inf.converged == 0 and inf.refine_steps == 0 and inf.rho > 1e-10
+    Xp = binv.invert(A, block=256)
+    assert torch.equal(X, Xp)
+    # the binding returns the iterate instead of raising
+    X2, info = binv.invert_mixed(A, block=256, from_fp64=True, max_refine=0)
+    assert not info["converged"] and torch.equal(X2, Xp)
+
+
+@pytest.mark.parametrize("from_fp64", [False, True])
+def test_non_finite_input_is_invalid(gpu, from_fp64):
+    import torch
+    from paper_2305_11103_amd import binv
+    A = wl.general_haar(300, 5, 1e2)
+    A[17, 250] = np.nan
+    with pytest.raises(binv.BinvError) as e:
+        binv.invert_mixed(torch.from_numpy(A).cuda(), block=128, from_fp64=from_fp64)
+    assert e.value.status == binv.BINV_E_INVALID

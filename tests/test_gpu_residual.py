@@ -117,7 +117,9 @@ def test_argument_errors(gpu):
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     rho = ctypes.c_double(-1.0)
     p = ctypes.c_void_p(A.data_ptr())
-    assert lib.binv_residual(ctx.handle, 8, p, 8, p, 8, 2, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
+    assert lib.binv_residual(ctx.handle, 8, p, 8, p, 8, 4, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
+    both = binv.BINV_RESID_ESTIMATE | binv.BINV_RESID_COMPENSATED
+    assert lib.binv_residual(ctx.handle, 8, p, 8, p, 8, both, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
     assert lib.binv_residual(ctx.handle, 8, p, 7, p, 8, 0, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
     assert lib.binv_residual(ctx.handle, -1, p, 8, p, 8, 0, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
     assert lib.binv_residual(ctx.handle, 8, None, 8, p, 8, 0, s, ctypes.byref(rho)) == binv.BINV_E_INVALID
