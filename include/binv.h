@@ -145,6 +145,29 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
                         double* X, int64_t ldx, const binv_opts* opts,
                         void* stream, int64_t* d_info);
 
+/* binv_invert for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The same blockwise sweep as binv_invert with BINV_F_NO_LOOKAHEAD (bitwise
+ * the same result), on the caller's stream only, whose workspace (the panels
+ * and, when d_info is NULL, the info word) is a static 64 MiB array that the
+ * library holds on every device it runs on until the process ends.  It calls
+ * no hipMalloc, hipFree or other allocating routine and creates no stream or
+ * event.  The workspace needed, in doubles, is
+ *   32 + 2 b n + b^2 + 512 b + 32768   (b = the largest block order),
+ * which must fit in 64 MiB (n = 7168 with b = 512, or
+ * n = 16384 with b = 224); larger problems are rejected with BINV_E_INVALID
+ * and a message giving the size they need.  Every call on one device shares
+ * that device's array, so calls whose work can overlap on one device (two
+ * streams, two host threads) race and corrupt each other; the array keeps the
+ * last call's contents, and a call writes every element it reads before
+ * reading it (the info word is cleared first).  Arguments, the in-place
+ * rule, d_info and BINV_F_SYNC are as for binv_invert; BINV_F_PIVOT and
+ * blocks of order > 2047 give BINV_E_INVALID; BINV_F_NO_LOOKAHEAD is implied.
+ * binv_create looks up each device's copy of the array; BINV_E_HIP if that
+ * failed. */
+binv_status binv_invert_noalloc(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                                const binv_opts* opts, void* stream, int64_t* d_info);
+
 /* ---------------------------------------------------------------------------
  * Mixed precision: the same blockwise sweep on an FP32 working copy (row
  * panels and Schur updates on FP32 MFMA with FP32 accumulation, every pivot

@@ -28,7 +28,7 @@ BINV_F_SYNC = 1
 BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
-EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
+EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_invert_noalloc", "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
            "binv_invert_mixed", "binv_residual", "binv_residual_matrix",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
@@ -104,6 +104,8 @@ def load_library():
     lib.binv_invert.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int64,
                                 ctypes.POINTER(_Opts), P, P]
     lib.binv_invert.restype = ctypes.c_int
+    lib.binv_invert_noalloc.argtypes = lib.binv_invert.argtypes
+    lib.binv_invert_noalloc.restype = ctypes.c_int
     lib.binv_set_timing.argtypes = [P, ctypes.c_uint32]
     lib.binv_set_timing.restype = ctypes.c_int
     lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
@@ -247,7 +249,7 @@ def _stream_handle(torch, device):
 
 
 def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True,
-           pivot=False):
+           pivot=False, _noalloc=False):
     """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
     inversion over the diagonal blocks `part` (or uniform blocks of `block`).
 
@@ -288,12 +290,21 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     lda = A.stride(0) if n > 0 else 1
     ldx = X.stride(0) if n > 0 else 1
     lib = load_library()
+    fn = lib.binv_invert_noalloc if _noalloc else lib.binv_invert
     with torch.cuda.device(dev):
-        st = lib.binv_invert(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(lda, n), ctypes.c_void_p(X.data_ptr()),
+        st = fn(ctx.handle, n, ctypes.c_void_p(A.data_ptr()), max(lda, n), ctypes.c_void_p(X.data_ptr()),
                 max(ldx, n), ctypes.byref(o), _stream_handle(torch, dev), info_ptr)
     del keep
     _check(st)
     return X
+
+
+def invert_noalloc(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None):
+    """invert() through binv_invert_noalloc: the serial sweep on the library's
+    static per-device workspace (no device allocation; sizes are limited, see
+    include/binv.h).  The caller allocates `out` (or passes inplace=True)."""
+    return invert(A, part=part, block=block, out=out, inplace=inplace, sync=sync, info=info, ctx=ctx,
+                  lookahead=False, _noalloc=True)
 
 
 def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=True,

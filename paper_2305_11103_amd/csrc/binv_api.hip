@@ -49,6 +49,50 @@ using binv::DevBuf;
 using binv::Level;
 using binv::PhaseTimer;
 
+// Static device workspace of binv_invert_noalloc: the panels (saved column
+// panel, row panel, pivot inverse) of its serial sweep and its info word, for
+// callers that cannot allocate device memory.  Every device the library runs
+// on holds one copy for the life of the process.  In host code `scratch`
+// names a host-side stand-in, not device memory: the device address of each
+// device's copy is looked up once (scratch_setup, called by binv_create with
+// that device current) and only that address is handed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+std::string g_scratch_err[kScratchDevices];
+
+// The device address of `device`'s copy of scratch (that device current).
+void scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return;
+  }
+  g_scratch_ptr[device] = ptr;
+}
+
+void* scratch_ptr(int device, std::string& why) {
+  if (device < 0 || device >= kScratchDevices) {
+    why = "device index beyond the static workspace table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) why = g_scratch_err[device].empty() ? "static workspace not set up" : g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 namespace {
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
@@ -583,6 +627,15 @@ binv_status binv_create(binv_ctx** ctx, int device) {
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->ncu = ncu;
+  // the device address of this device's static workspace, once per device
+  int prev = 0;
+  if (hipGetDevice(&prev) == hipSuccess) {
+    if (prev == device || hipSetDevice(device) == hipSuccess) {
+      scratch_setup(device);
+      if (prev != device) (void)hipSetDevice(prev);
+    }
+  }
+  (void)hipGetLastError();
   *ctx = c;
   return BINV_OK;
 }
@@ -1066,6 +1119,91 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     else
       st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
     if (st != BINV_OK) goto out;
+  }
+  if (flags & BINV_F_SYNC) {
+    long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("sync: ") + hipGetErrorString(e)); goto out; }
+    if (h < 0) st = fail(BINV_E_INVALID, "A holds a NaN or an infinity");
+    if (h > 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
+  }
+out:
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+binv_status binv_invert_noalloc(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                                const binv_opts* opts, void* stream, int64_t* d_info) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (n > 0 && (!A || !X)) return fail(BINV_E_INVALID, "A or X is NULL");
+  if (n > 0 && (lda < n || ldx < n)) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  const bool inplace = (A == X);
+  if (inplace && lda != ldx) return fail(BINV_E_INVALID, "in-place call needs lda == ldx");
+  if (!inplace && n > 0) {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + (n - 1) * lda + n);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + (n - 1) * ldx + n);
+    if (a0 < x1 && x0 < a1) return fail(BINV_E_INVALID, "A and X overlap without being the same matrix");
+  }
+  const uint32_t flags = opts ? opts->flags : 0u;
+  if (flags & BINV_F_PIVOT) return fail(BINV_E_INVALID, "binv_invert_noalloc does not pivot across blocks");
+  std::vector<int32_t> part;
+  {
+    binv_status pst = parse_partition(n, opts, part);
+    if (pst != BINV_OK) return pst;
+  }
+  int bmax = 0;
+  for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  if (bmax > 2047) return fail(BINV_E_INVALID, "binv_invert_noalloc needs diagonal blocks of order <= 2047");
+  // workspace in doubles: the info word (padded to 32 doubles), the serial
+  // sweep's column panel, row panel and pivot inverse, and two sets of the
+  // nested pivot sweep's panels (sub-blocks of at most 128)
+  const size_t nb = (size_t)bmax * (size_t)n, sub = 128 * (size_t)bmax;
+  const size_t need = 32 + 2 * nb + (size_t)bmax * bmax + 4 * sub + 2 * 128 * 128;
+  if (need * sizeof(double) > kScratchBytes)
+    return fail(BINV_E_INVALID, "binv_invert_noalloc: n = " + std::to_string(n) + " with blocks of " +
+                                    std::to_string(bmax) + " needs " + std::to_string(need * sizeof(double)) +
+                                    " bytes of workspace; the static workspace holds " +
+                                    std::to_string(kScratchBytes));
+  std::string why;
+  double* base = (double*)scratch_ptr(ctx->device, why);
+  if (!base) return fail(BINV_E_HIP, "binv_invert_noalloc: " + why);
+
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  binv_status st = BINV_OK;
+  long long* info = d_info ? (long long*)d_info : (long long*)base;
+  {
+    // a context of slices of the static workspace: the sweep's ensure() calls
+    // find them large enough and never allocate; no timing, no side streams
+    binv_ctx w;
+    w.device = ctx->device;
+    w.ncu = ctx->ncu;
+    double* q = base + 32;
+    auto take = [&](DevBuf& d, size_t doubles) {
+      d.borrow(q, doubles * sizeof(double));
+      q += doubles;
+    };
+    take(w.lv[0].ct[0], nb);
+    take(w.lv[0].r[0], nb);
+    take(w.lv[0].p[0], (size_t)bmax * bmax);
+    for (int h = 0; h < 2; ++h) {
+      take(w.lv[1].ct[h], sub);
+      take(w.lv[1].r[h], sub);
+      take(w.lv[1].p[h], 128 * 128);
+    }
+    hipError_t e = binv::launch_zero_info(info, s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
+    if (n > 0) {
+      e = binv::launch_copy2d_check(A, lda, X, ldx, n, n, info, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
+      if ((st = sweep(&w, 0, n, X, ldx, part, s, info, 0, false)) != BINV_OK) goto out;
+    }
   }
   if (flags & BINV_F_SYNC) {
     long long h = 0;

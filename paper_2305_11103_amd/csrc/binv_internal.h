@@ -202,12 +202,24 @@ hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats,
 // binv_api.hip: records the thread-local message returned by binv_last_error
 void set_error(const std::string& msg);
 
-// A growable device buffer.
+// A growable device buffer, or (borrowed) a fixed slice of memory the
+// library does not own, which never grows.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;
+  void borrow(void* ptr, size_t n) {
+    p = ptr;
+    bytes = n;
+    borrowed = true;
+  }
   binv_status ensure(size_t want) {
     if (want <= bytes) return BINV_OK;
+    if (borrowed) {
+      binv::set_error("a fixed workspace slice of " + std::to_string(bytes) + " bytes cannot hold " +
+                      std::to_string(want));
+      return BINV_E_INVALID;
+    }
     if (p) {
       hipError_t e = hipFree(p);
       p = nullptr;
@@ -226,9 +238,10 @@ struct DevBuf {
     return BINV_OK;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
 };
 
