@@ -63,6 +63,25 @@ def inverse_adjugate(M) -> list[list[Fraction]]:
     return inv
 
 
+def inverse_rational_gj(M) -> list[list[Fraction]]:
+    """Exact inverse by Gauss-Jordan elimination in rationals (any nonzero
+    pivot: exact arithmetic needs no pivoting for accuracy); O(n^3)."""
+    n = len(M)
+    W = [list(row) + [Fraction(int(i == j)) for j in range(n)] for i, row in enumerate(M)]
+    for c in range(n):
+        r = next((i for i in range(c, n) if W[i][c] != 0), None)
+        if r is None:
+            raise ZeroDivisionError("singular")
+        W[c], W[r] = W[r], W[c]
+        q = 1 / W[c][c]
+        W[c] = [x * q for x in W[c]]
+        for i in range(n):
+            if i != c and W[i][c] != 0:
+                f = W[i][c]
+                W[i] = [a - f * b for a, b in zip(W[i], W[c])]
+    return [row[n:] for row in W]
+
+
 def matmul(A, B):
     n, q, p = len(A), len(B), len(B[0])
     return [[sum((A[i][t] * B[t][j] for t in range(q)), Fraction(0)) for j in range(p)] for i in range(n)]
