@@ -397,6 +397,113 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_levels(args):
+    """The paper's own parallel algorithm (§5, binv_invert_batched_levels) on
+    the batched workload's small matrices: 100000 SPD 5 x 5 (Table 2 gives
+    blocks [2, 3]) plus 20000 SPD of order uniform in [8, 64], each split by
+    Table 2's scheme, against the blockwise sweep's register tiers on the same
+    plan (the same partitions)."""
+    import torch
+
+    import oracle
+    from oracle import level_scheme as ls
+    from paper_2305_11103_amd import binv, workloads
+
+    rng = np.random.default_rng(workloads.stream_seed(4, 9))
+    sizes = [5] * 100000 + [int(x) for x in rng.integers(8, 65, 20000)]
+    parts = [binv.level_partition(m) for m in sizes]
+    log("bench: generating the level-scheme batch (100000 x 5^2 + 20000 x U{8..64}^2 SPD)")
+    mats = workloads.spd_gram_batch(sizes, workloads.stream_seed(4, 10))
+    ctx = binv.default_context(0)
+    plan = binv.Batch(sizes, parts=parts, ctx=ctx)
+    A = torch.from_numpy(plan.pack(mats)).to("cuda:0")
+    X = torch.empty_like(A)
+    Xs = torch.empty_like(A)
+    info = torch.empty(plan.count, dtype=torch.int32, device="cuda:0")
+    # the scheme's own flop count, per distinct partition times its multiplicity
+    from collections import Counter
+    cnt = Counter(tuple(p) for p in parts)
+    lvl_flops = sum(ls.level_scheme_flops(list(p)) * c for p, c in cnt.items())
+    for i in range(args.warmup):
+        plan.invert_levels(A, out=X, info=info)
+        plan.invert(A, out=Xs, info=info, graph=True)
+        log(f"bench: warmup {i + 1}/{args.warmup} done")
+    ctx.set_timing(["small"])
+    ctx.get_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.invert_levels(A, out=X, info=info, sync=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timing = ctx.get_timing()
+    ctx.set_timing([])
+    ms_step = wall * 1e3 / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.invert(A, out=Xs, info=info, graph=True, sync=False)
+    torch.cuda.synchronize()
+    ms_sweep = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"bench: level scheme {ms_step:.3f} ms/batch, blockwise sweep tiers {ms_sweep:.3f} ms/batch")
+    plan.invert_levels(A, out=X, info=info)
+    inf = info.cpu().numpy()
+    rho_dev = plan.residual(A, X).cpu().numpy()
+    Xh = plan.unpack(X.cpu().numpy())
+    pick = np.unique(np.concatenate([np.random.default_rng(5).choice(len(sizes), 200, replace=False),
+                                     np.argsort(sizes)[-20:]]))
+    err = 0.0
+    for i in pick:
+        Xo = ls.level_scheme_inverse(mats[i], parts[i])
+        tol = 64 * sizes[i] * 2.0 ** -53 * np.linalg.cond(mats[i]) * np.max(np.abs(Xo))
+        err = max(err, float(np.max(np.abs(Xh[i] - Xo)) / tol))
+    rho = max(oracle.residual_stats(mats[i], Xh[i])["rho"] for i in pick)
+    ok = bool((inf == 0).all() and float(rho_dev.max()) <= 1e-12 and rho <= 1e-12 and err <= 1.0)
+    log(f"bench: device max rho {rho_dev.max():.3e}, sampled oracle rho {rho:.3e}, "
+        f"max error / tolerance {err:.3f}, ok={ok}")
+    d_ms, d_cnt, d_fl = timing["small"]
+    avg_ms = d_ms / max(d_cnt, 1)
+    cpu = None
+    if not args.no_cpu:
+        log("bench: timing the oracle's level scheme on a sample of the batch")
+        order = np.random.default_rng(17).permutation(len(sizes))
+        t0 = time.perf_counter()
+        fl, done = 0.0, 0
+        while time.perf_counter() - t0 < args.cpu_budget and done < len(order):
+            i = int(order[done])
+            ls.level_scheme_inverse(mats[i], parts[i])
+            fl += 2.0 * sizes[i] ** 3
+            done += 1
+        tc = time.perf_counter() - t0
+        cpu = {"value": fl / tc / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"the oracle's level scheme (numpy, one thread) on {done} matrices of the batch in "
+                         f"random order, {tc:.1f} s, rate 2 m^3 per matrix / time"}
+    out = {
+        "metric": METRIC,
+        "value": round(plan.flops / (ms_step * 1e-3) / 1e12 if ok else 0.0, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "paper's level scheme (section 5) on 100000 x 5^2 + 20000 x U{8..64}^2 SPD, "
+                               "Table 2 partitions", "matrices": plan.count, "flops_2m3": plan.flops,
+                   "flops_level_scheme": lvl_flops},
+        "valid": ok, "rho_max_all_device": float(rho_dev.max()), "rho_max_sampled": rho,
+        "max_error_over_tolerance_sampled": err,
+        "solves_per_s": round(plan.count / (ms_step * 1e-3), 1),
+        "blockwise_sweep_ms_per_batch": round(ms_sweep, 4),
+        "speedup_vs_blockwise_sweep": round(ms_sweep / ms_step, 3),
+        "roofline": {"bound": "alu", "kernel": "k_level_scheme (one workgroup per matrix, all four tiers)",
+                     "achieved": round(d_fl / max(d_cnt, 1) / (avg_ms * 1e-3) / 1e12, 4) if d_ms > 0 else 0.0,
+                     "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": round(d_fl / max(d_cnt, 1) / (avg_ms * 1e-3) / 1e12 / PEAK_FP64, 5) if d_ms > 0 else 0.0,
+                     "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": d_cnt,
+                     "flops_counted": "the scheme's own flops (n^3 (3 - 1/N_k) for uniform blocks)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_mixed(args):
     """Config 3 at each cond: the paper's unpivoted FP64 sweep, the FP64 sweep
     with block-row pivoting, and the two paths that end at the target: FP64
@@ -733,7 +840,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve", "levels"], default="plain")
     ap.add_argument("--gen", choices=["device", "host"], default="device",
                     help="where the plain workload's Haar factor is formed")
     ap.add_argument("--requests", type=int, default=5000)
@@ -751,7 +858,8 @@ def main():
               f"(the batched and served forms shard with no communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
-    {"plain": bench_plain, "batched": bench_batched, "mixed": bench_mixed, "serve": bench_serve}[args.workload](args)
+    {"plain": bench_plain, "batched": bench_batched, "mixed": bench_mixed, "serve": bench_serve,
+     "levels": bench_levels}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -275,6 +275,37 @@ binv_status binv_batch_query(const binv_batch* plan, int64_t* count, int64_t* to
 binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, int32_t* d_info, uint32_t flags,
                                 void* stream);
 
+/* The paper's parallel algorithm (§5) on every matrix of a plan, instead of
+ * the blockwise sweep: each matrix's diagonal blocks (a power-of-two count
+ * N_k, orders 1..4; binv_level_partition gives the scheme of §5.1) are
+ * inverted bottom-up by Eq. (ad) over N_s = 2 N_k - 1 steps whose work the
+ * step number fixes (Tables 4 and 5): the closed-form inverses of the
+ * diagonal blocks (◊), the products -A^-1 B and -D^-1 C (→, ←), the Schur
+ * complements S_A and S_D (∼), which are inverted by the same scheme one
+ * level down in the provisional sets of §5.3, and the products with their
+ * inverses (↑, ↓).  No pivoting: every diagonal block and Schur complement
+ * met must be invertible (SPD inputs guarantee it).  It costs
+ * n^3 (3 - 1/N_k) flops for uniform blocks against the sweep's 2 n^3.  One
+ * workgroup per matrix with M_inv and the provisional sets on chip.
+ * A, X, d_info and in-place use as for binv_invert_batched; d_info[i] is the
+ * 1-based first row of the first block (earliest step, then lowest block)
+ * whose determinant was exactly zero.  flags: BINV_F_SYNC (BINV_F_GRAPH is
+ * accepted and has no effect: the call is one launch per order tier).
+ * Errors: BINV_E_INVALID for an order > 64, a block count that is not a
+ * power of two, a block order > 4, or provisional sets beyond the on-chip
+ * store (2.5 x 64^2 doubles at orders 33..64, 2.5 M^2 for the tier bound M
+ * below); checked on the first call, naming the matrix. */
+binv_status binv_invert_batched_levels(binv_batch* plan, const double* A, double* X, int32_t* d_info,
+                                       uint32_t flags, void* stream);
+
+/* The partition of §5.1 (Table 2): N_k = 2^(floor(log2 m) - 1) diagonal
+ * blocks (1 for m < 4) of orders floor(m / N_k), the remainder added one by
+ * one to the last blocks, so every order is 2, 3 or 4 for m >= 2.  Writes N_k
+ * to *k and, if part is not NULL, the orders to part[0 .. N_k) (capacity:
+ * its length).  Host only.  Errors: BINV_E_INVALID for m < 1, k NULL or a
+ * capacity below N_k. */
+binv_status binv_level_partition(int32_t m, int32_t capacity, int32_t* k, int32_t* part);
+
 /* Autotuner for the register-resident tiers (orders <= 128).  Each tier has
  * several launch shapes (rows per lane, columns per wave, waves per matrix,
  * matrices per workgroup) that compute bitwise-identical results; this call

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbinv.so")
-SOURCES = ["kernels.hip", "batched.hip", "mixed.hip", "binv_api.hip", "batched_api.hip", "server.hip"]
+SOURCES = ["kernels.hip", "batched.hip", "mixed.hip", "levels.hip", "binv_api.hip", "batched_api.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

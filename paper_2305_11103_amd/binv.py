@@ -32,6 +32,7 @@ EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_invert_noalloc", 
            "binv_invert_mixed", "binv_residual", "binv_residual_matrix",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
+           "binv_invert_batched_levels", "binv_level_partition",
            "binv_server_create", "binv_submit", "binv_poll", "binv_next_done", "binv_server_stats",
            "binv_server_destroy",
            "binv_last_error", "binv_version")
@@ -152,6 +153,11 @@ def load_library():
     lib.binv_batch_shape.restype = ctypes.c_int
     lib.binv_batch_residual.argtypes = [P, P, P, P, P]
     lib.binv_batch_residual.restype = ctypes.c_int
+    lib.binv_invert_batched_levels.argtypes = [P, P, P, P, ctypes.c_uint32, P]
+    lib.binv_invert_batched_levels.restype = ctypes.c_int
+    lib.binv_level_partition.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32)]
+    lib.binv_level_partition.restype = ctypes.c_int
     lib.binv_last_error.argtypes = []
     lib.binv_last_error.restype = ctypes.c_char_p
     lib.binv_version.argtypes = []
@@ -382,6 +388,15 @@ def residual_matrix(A, X, ctx=None):
     return R, rho.value
 
 
+def level_partition(m):
+    """The diagonal-block orders of §5.1's partitioning scheme (Table 2)."""
+    k = ctypes.c_int32()
+    _check(load_library().binv_level_partition(int(m), 0, ctypes.byref(k), None))
+    part = (ctypes.c_int32 * max(k.value, 1))()
+    _check(load_library().binv_level_partition(int(m), k.value, ctypes.byref(k), part))
+    return list(part[:k.value])
+
+
 def batch_shape(tier, shape):
     """Launch shape (rows/lane, cols/wave, waves/matrix, matrices/workgroup)."""
     out = (ctypes.c_int32 * 4)()
@@ -440,6 +455,24 @@ class Batch:
             st = load_library().binv_invert_batched(self._h, ctypes.c_void_p(A.data_ptr()),
                                                     ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(info.data_ptr()),
                                                     flags, _stream_handle(torch, A.device.index or 0))
+        _check(st)
+        return X, info
+
+    def invert_levels(self, A, out=None, info=None, sync=True, inplace=False):
+        """Every matrix by the paper's level scheme (binv_invert_batched_levels);
+        returns (X, info)."""
+        import torch
+        if A.dtype != torch.float64 or not A.is_cuda or A.numel() != self.total_elems or not A.is_contiguous():
+            raise ValueError("A must be a contiguous float64 CUDA buffer of the plan's packed size")
+        X = A if inplace else (out if out is not None else torch.empty_like(A))
+        if info is None:
+            info = torch.empty(max(self.count, 1), dtype=torch.int32, device=A.device)
+        with torch.cuda.device(A.device):
+            st = load_library().binv_invert_batched_levels(self._h, ctypes.c_void_p(A.data_ptr()),
+                                                           ctypes.c_void_p(X.data_ptr()),
+                                                           ctypes.c_void_p(info.data_ptr()),
+                                                           BINV_F_SYNC if sync else 0,
+                                                           _stream_handle(torch, A.device.index or 0))
         _check(st)
         return X, info
 

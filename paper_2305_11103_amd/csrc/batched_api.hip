@@ -92,6 +92,12 @@ struct binv_batch {
   hipStream_t cap = nullptr;
   std::vector<int32_t> bounds_host;
   std::vector<int32_t> bnd_index;
+  // the paper's level scheme (binv_invert_batched_levels): matrices grouped
+  // by tier (orders <= 8, 16, 32, 64), formed on its first call
+  bool lvl_ready = false;
+  int64_t lvl_first[4] = {0}, lvl_count[4] = {0};
+  double lvl_flops[4] = {0};  // the scheme's own flops per tier
+  void* d_lvl_order = nullptr;
 };
 
 namespace {
@@ -335,7 +341,7 @@ binv_status binv_batch_destroy(binv_batch* b) {
   if (!b) return BINV_OK;
   if (b->cap) (void)hipStreamSynchronize(b->cap);
   free_bindings(b);
-  for (void* p : {b->d_mats, b->d_order, b->d_bounds, b->d_ws})
+  for (void* p : {b->d_mats, b->d_order, b->d_bounds, b->d_ws, b->d_lvl_order})
     if (p) (void)hipFree(p);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
@@ -386,6 +392,94 @@ binv_status binv_invert_batched(binv_batch* b, const double* A, double* X, int32
   } else {
     binv_status st = enqueue(b, A, X, d_info, s, true);
     if (st != BINV_OK) return st;
+  }
+  if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));
+  return BINV_OK;
+}
+
+binv_status binv_level_partition(int32_t m, int32_t capacity, int32_t* k, int32_t* part) {
+  if (m < 1 || !k) return bfail(BINV_E_INVALID, "order must be positive and k not NULL");
+  int nk = 1;
+  if (m >= 4) {
+    int lg = 0;
+    while ((2 << lg) <= m) ++lg;  // floor(log2 m)
+    nk = 1 << (lg - 1);
+  }
+  *k = nk;
+  if (!part) return BINV_OK;
+  if (capacity < nk) return bfail(BINV_E_INVALID, "part holds fewer entries than the block count");
+  const int q = m / nk, r = m - q * nk;
+  for (int i = 0; i < nk; ++i) part[i] = q + (i >= nk - r ? 1 : 0);
+  return BINV_OK;
+}
+
+binv_status binv_invert_batched_levels(binv_batch* b, const double* A, double* X, int32_t* d_info, uint32_t flags,
+                                       void* stream) {
+  if (!b) return bfail(BINV_E_INVALID, "plan is NULL");
+  if (flags & ~(BINV_F_SYNC | BINV_F_GRAPH)) return bfail(BINV_E_INVALID, "unknown flags");
+  if (b->count == 0) return BINV_OK;
+  if (!A || !X || !d_info) return bfail(BINV_E_INVALID, "A, X and d_info must be device pointers");
+  if (A != X) {
+    const char* a0 = (const char*)A;
+    const char* a1 = (const char*)(A + b->total);
+    const char* x0 = (const char*)X;
+    const char* x1 = (const char*)(X + b->total);
+    if (a0 < x1 && x0 < a1) return bfail(BINV_E_INVALID, "A and X overlap without being the same buffer");
+  }
+  if (!b->lvl_ready) {
+    std::vector<int32_t> tiers[4];
+    for (int64_t i = 0; i < b->count; ++i) {
+      const int mi = b->m[i];
+      const int bi = b->bnd_index[i];
+      const int nk = b->bnd_index[i + 1] - bi - 1;
+      const std::string at = " (matrix " + std::to_string(i) + ")";
+      if (mi > binv::level_tier_limit(3)) return bfail(BINV_E_INVALID, "the level scheme takes orders <= 64" + at);
+      if (nk & (nk - 1)) return bfail(BINV_E_INVALID, "the block count must be a power of two" + at);
+      for (int j = 0; j < nk; ++j)
+        if (b->bounds_host[bi + j + 1] - b->bounds_host[bi + j] > 4)
+          return bfail(BINV_E_INVALID, "the level scheme's diagonal blocks have orders <= 4" + at);
+      int t = 0;
+      while (mi > binv::level_tier_limit(t)) ++t;
+      // the provisional sets: every level-l unit's square
+      size_t need = 0;
+      double fl = 0.0;
+      for (int j = 0; j < nk; ++j) {
+        const double bj = b->bounds_host[bi + j + 1] - b->bounds_host[bi + j];
+        fl += 2.0 * bj * bj * bj * nk;  // one closed-form inverse per block and ◊ step (N_k of them)
+      }
+      for (int l = 1; (1 << l) <= nk; ++l)
+        for (int v = 0; v < (nk >> l); ++v) {
+          const int u0 = b->bounds_host[bi + (v << l)];
+          const int uh = b->bounds_host[bi + (v << l) + (1 << (l - 1))];
+          const int u1 = b->bounds_host[bi + ((v + 1) << l)];
+          need += (size_t)(u1 - u0) * (u1 - u0);
+          // per unit: →, ← and ∼ 4 na nd (na + nd), ↑↓ 2 na nd (na + nd),
+          // once per inversion of the matrices containing the unit
+          const double na = uh - u0, nd = u1 - uh;
+          fl += 6.0 * na * nd * (na + nd) * (double)(nk >> l);
+        }
+      if (need > binv::level_tier_tmax(t))
+        return bfail(BINV_E_INVALID, "the partition's provisional sets exceed the tier's on-chip store" + at);
+      tiers[t].push_back((int32_t)i);
+      b->lvl_flops[t] += fl;
+    }
+    std::vector<int32_t> order;
+    for (int t = 0; t < 4; ++t) {
+      b->lvl_first[t] = (int64_t)order.size();
+      b->lvl_count[t] = (int64_t)tiers[t].size();
+      order.insert(order.end(), tiers[t].begin(), tiers[t].end());
+    }
+    binv_status st = upload(order, &b->d_lvl_order);
+    if (st != BINV_OK) return st;
+    b->lvl_ready = true;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int t = 0; t < 4; ++t) {
+    binv::PhaseTimer tm(b->ctx, 0, BINV_PHASE_SMALL, s);
+    if (tm.on()) tm.flops = b->lvl_flops[t];
+    BHIP(binv::launch_level_tier(t, A, X, (const binv::SmallMat*)b->d_mats,
+                                 (const int32_t*)b->d_lvl_order + b->lvl_first[t], b->lvl_count[t],
+                                 (const int32_t*)b->d_bounds, d_info, s));
   }
   if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));
   return BINV_OK;

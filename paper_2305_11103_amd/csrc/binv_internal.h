@@ -199,6 +199,14 @@ hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats,
                                double* work, double target, const double* targets, int max_steps, double* rho,
                                int32_t* steps, hipStream_t s);
 
+// levels.hip: the paper's parallel algorithm (§5) on packed small matrices,
+// one workgroup per matrix; tier t takes orders <= level_tier_limit(t) (8, 16,
+// 32, 64) with provisional sets of at most level_tier_tmax(t) doubles.
+int level_tier_limit(int t);
+size_t level_tier_tmax(int t);
+hipError_t launch_level_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
+                             int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s);
+
 // binv_api.hip: records the thread-local message returned by binv_last_error
 void set_error(const std::string& msg);
 

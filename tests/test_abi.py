@@ -69,3 +69,23 @@ def test_binding_shares_torch_hip_runtime():
     import ast
     libs = ast.literal_eval(out.stdout.strip().splitlines()[-1])
     assert len(libs) == 1 and "torch" in libs[0], libs
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_level_partition_is_table2():
+    """binv_level_partition (host only) against the rows printed in Table 2
+    and the oracle's partitioner for every order up to 4096."""
+    from oracle import level_scheme as ls
+    from paper_2305_11103_amd import binv
+    rows = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "table2_partitions.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split(":")
+            rows[int(k)] = [int(x) for x in v.split()]
+    for m, blocks in rows.items():
+        assert binv.level_partition(m) == blocks
+    for m in range(1, 4097):
+        assert binv.level_partition(m) == ls.table2_partition(m)
+    with pytest.raises(binv.BinvError):
+        binv.level_partition(0)
