@@ -397,6 +397,91 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_small(args):
+    """Config 1: one FP64 256 x 256 matrix (U[-1, 1] + 256 I), a 4 x 4 grid of
+    64-blocks.  Latency-bound: reported in microseconds per inversion, eager
+    (every launch enqueued by the host) and replayed from a HIP graph, each
+    as the latency of one synchronized call (p50 / p99) and as the back-to-back
+    rate."""
+    import torch
+
+    import oracle
+    from paper_2305_11103_amd import binv, workloads
+
+    n, part = 256, [64] * 4
+    A_np = workloads.diag_dominant(n, workloads.stream_seed(1, 0))
+    A = torch.from_numpy(A_np).to("cuda:0")
+    X = torch.empty_like(A)
+    ctx = binv.default_context(0)
+    reps = max(args.steps, 200)
+    res = {}
+    # eager with and without the lookahead's side streams; the graph records
+    # the one-stream schedule (the library captures only that one)
+    for mode in ("eager_lookahead", "eager", "graph"):
+        g = mode == "graph"
+        look = mode == "eager_lookahead"
+        for _ in range(max(args.warmup, 3)):
+            binv.invert(A, part=part, out=X, ctx=ctx, sync=False, graph=g, lookahead=look)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            binv.invert(A, part=part, out=X, ctx=ctx, sync=False, graph=g, lookahead=look)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e6)
+        lat.sort()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            binv.invert(A, part=part, out=X, ctx=ctx, sync=False, graph=g, lookahead=look)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) * 1e6 / reps
+        res[mode] = {"p50_us": round(lat[len(lat) // 2], 2), "p99_us": round(lat[int(0.99 * (len(lat) - 1))], 2),
+                     "back_to_back_us": round(per, 2)}
+        log(f"bench: {mode}: p50 {res[mode]['p50_us']} us, p99 {res[mode]['p99_us']} us, "
+            f"back to back {res[mode]['back_to_back_us']} us per inversion")
+    Xh = X.cpu().numpy()
+    Xo = oracle.gj_inverse(A_np)
+    err = float(np.max(np.abs(Xh - Xo)) / np.max(np.abs(Xo)))
+    rho = oracle.residual_stats(A_np, Xh)["rho"]
+    ok = bool(err <= 64 * n * 2.0 ** -53 * np.linalg.cond(A_np) and rho <= 1e-10)
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < min(args.cpu_budget, 5.0):
+            oracle.gj_inverse(A_np)
+            k += 1
+        t_gj = (time.perf_counter() - t0) / k
+        t0 = time.perf_counter()
+        oracle.blockwise_inverse(A_np, part)
+        t_bw = time.perf_counter() - t0
+        cpu = {"value": 2.0 * n ** 3 / t_gj / 1e12, "unit": "TFLOP/s", "cores": cores_used(), "kind": "oracle",
+               "sample": f"Gauss-Jordan with partial pivoting (oracle) on the same matrix, {k} runs, "
+                         f"{t_gj * 1e6:.0f} us each; the oracle's blockwise inversion {t_bw * 1e6:.0f} us"}
+    flops = 2.0 * n ** 3
+    best = res["graph"]["back_to_back_us"]
+    out = {
+        "metric": METRIC,
+        "value": round(flops / (best * 1e-6) / 1e12 if ok else 0.0, 5),
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 3),
+        "ms_per_step": round(best / 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "plain FP64 blockwise inversion, n=256, 4x4 grid of 64-blocks, U[-1,1] + 256 I",
+                   "n": n, "block": 64, "k": 4},
+        "valid": ok, "max_rel_err_vs_oracle": err, "rho": rho,
+        "latency_us": res,
+        "solves_per_s": round(1e6 / best, 1),
+        "p50_ms": round(res["graph"]["p50_us"] / 1e3, 5), "p99_ms": round(res["graph"]["p99_us"] / 1e3, 5),
+        "roofline": {"bound": "latency", "kernel": "whole inversion (about 17 launches, replayed as one graph)",
+                     "achieved": round(flops / (best * 1e-6) / 1e12, 5), "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": round(flops / (best * 1e-6) / 1e12 / PEAK_FP64, 6), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_levels(args):
     """The paper's own parallel algorithm (§5, binv_invert_batched_levels) on
     the batched workload's small matrices: 100000 SPD 5 x 5 (Table 2 gives
@@ -840,7 +925,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve", "levels"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve", "levels", "small"], default="plain")
     ap.add_argument("--gen", choices=["device", "host"], default="device",
                     help="where the plain workload's Haar factor is formed")
     ap.add_argument("--requests", type=int, default=5000)
@@ -859,7 +944,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     {"plain": bench_plain, "batched": bench_batched, "mixed": bench_mixed, "serve": bench_serve,
-     "levels": bench_levels}[args.workload](args)
+     "levels": bench_levels, "small": bench_small}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -77,9 +77,21 @@ typedef enum {
                              binv_residual; 4 * 64 * n^2 flops instead of
                              2 n^3) for n >= 192; the full residual is formed
                              only when a Newton-Schulz step needs it */
-#define BINV_F_GRAPH 4u  /* batched calls: capture the whole launch sequence in
-                             a HIP graph on first use and replay it (re-captured
-                             when the A, X or info pointers change) */
+#define BINV_F_GRAPH 4u  /* capture the call's whole launch sequence in a HIP
+                             graph on first use and replay it afterwards.
+                             Batched calls: one graph per plan, re-captured
+                             when the A, X or info pointers change.
+                             binv_invert (with BINV_F_NO_LOOKAHEAD, required
+                             when there are two blocks or more: the two-stream
+                             lookahead schedule is not captured,
+                             BINV_E_INVALID otherwise): graphs cached in the
+                             context (at most 16, least recently used
+                             replaced) keyed by n, the leading dimensions, the
+                             A, X and info pointers, the flags and the
+                             partition; the first call of a key runs eagerly
+                             (sizing the workspace), then captures; a key is
+                             re-captured when the context's workspace has moved
+                             since.  A replay reads A as it is at replay time. */
 #define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only.
                              By default, block p+1's diagonal block is updated
                              first, then block p+1's pivot block is inverted
@@ -144,6 +156,54 @@ binv_status binv_destroy(binv_ctx* ctx);
 binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda,
                         double* X, int64_t ldx, const binv_opts* opts,
                         void* stream, int64_t* d_info);
+
+/* Steps [p_begin, p_end) of binv_invert's blockwise sweep, in place on W
+ * (n x n, leading dimension ldw, device): the stepid of §5 as a resumable
+ * control variable for this sweep.  Step p applies Eq. (a) for diagonal block
+ * p (pivot inversion, row panel, Schur update with the column panel), so
+ * after steps 0..p the working matrix holds the partial sweep of the leading
+ * block L = blocks 0..p (§4.2's in-place procedure, stopped there):
+ *   [[ L^-1,       L^-1 B       ],
+ *    [ -C L^-1,    D - C L^-1 B ]]   (B, C, D the rest of A)
+ * and after step k-1 (k = number of blocks) W = A^-1.  W must hold A before
+ * step 0 and exactly the state the previous range left before any later
+ * range: the library keeps nothing between calls, so the state may be copied
+ * out (to the host, a file) and copied back, to this or another device
+ * buffer, and the sweep resumed later.  Results are bitwise those of
+ * binv_invert for every way of cutting [0, k) into ranges.  opts as for
+ * binv_invert (same partition on every call); BINV_F_PIVOT is rejected (the
+ * pivoted sweep's row order would be state too).  p_end < 0 means k.  d_info
+ * (optional device int64): set to 0 when p_begin == 0, then the 1-based row of
+ * the first exactly-zero pivot (kept across calls); when NULL, an internal
+ * word cleared by every call, so only the call's own steps are reported.
+ * BINV_F_SYNC: return BINV_E_SINGULAR once that word is set.  Errors: BINV_E_INVALID for a range
+ * outside 0 <= p_begin <= p_end <= k and the argument errors of
+ * binv_invert. */
+binv_status binv_sweep_steps(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, const binv_opts* opts,
+                             int32_t p_begin, int32_t p_end, void* stream, int64_t* d_info);
+
+/* Out-of-core inversion: W (n x n, row-major, leading dimension ldw) lives
+ * in HOST memory and is inverted in place by binv_invert's blockwise sweep
+ * while the device holds only the current block's panels and two slabs of
+ * rows, so n may exceed what the device memory holds (§5's design constraint
+ * of blocks kept outside memory, with the work done in a predefined sequence
+ * of steps).  Step p copies block p's rows and column panel to the device,
+ * inverts the pivot block and forms the row panel there, then streams every
+ * slab of rows in, applies the trailing update to it and copies it back,
+ * alternating two device streams so the copies of one slab overlap the
+ * update of the other.  device_bytes bounds the call's device memory:
+ * 8 (4 b n + b^2 + 4 (64 b + 4096)) + 256 bytes for the panels (b = the
+ * largest block order) plus 16 n bytes per row of slab height (rounded down
+ * to a multiple of 128 rows when at least 128); BINV_E_INVALID below one row.
+ * The result is bitwise that of binv_invert.  Page-locked host memory
+ * (hipHostMalloc) makes the copies asynchronous; pageable memory works too.
+ * Synchronous.  *singular_row (may be NULL): 0, or the 1-based row of the
+ * first exactly-zero pivot (status BINV_E_SINGULAR; W is then undefined).
+ * opts as for binv_invert (BINV_F_GRAPH and BINV_F_NO_LOOKAHEAD have no
+ * effect); BINV_F_PIVOT and blocks of order > 2047 give BINV_E_INVALID.  The
+ * host matrix is not checked for NaN or infinity. */
+binv_status binv_invert_host(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, const binv_opts* opts,
+                             size_t device_bytes, void* stream, int64_t* singular_row);
 
 /* binv_invert for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
@@ -371,7 +431,10 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * forgets the ticket.  A finished request keeps its memory until it is
  * polled; the server then keeps the block for reuse by later requests (at
  * most a quarter of the budget in cached blocks, freed by
- * binv_server_destroy).  Errors: BINV_E_NOMEM from binv_submit when the request alone
+ * binv_server_destroy).  Everything the server holds counts against the
+ * budget, cached blocks and the workspace of its worker contexts included;
+ * to admit a request it frees cached blocks and idle workers' workspace
+ * before waiting.  Errors: BINV_E_NOMEM from binv_submit when the request alone
  * exceeds the budget; BINV_E_SINGULAR (and the other codes) from binv_poll
  * for a request that failed.
  * --------------------------------------------------------------------------- */
@@ -402,7 +465,10 @@ binv_status binv_poll(binv_server* server, uint64_t ticket, double* X, int x_is_
  * it; a ticket collected without this call is skipped here. */
 binv_status binv_next_done(binv_server* server, int64_t wait_us, uint64_t* ticket);
 
-/* Device bytes currently held, the most ever held (never above the budget),
+/* Device bytes the server holds or has reserved (request blocks of admitted
+ * requests and those kept for reuse, the workspace its worker contexts and
+ * its small-request round buffers have grown to, and the workspace reserved
+ * for requests still running), the most ever held (never above the budget),
  * and requests finished so far.  Any pointer may be NULL. */
 binv_status binv_server_stats(binv_server* server, size_t* used_bytes, size_t* peak_bytes, int64_t* completed);
 /* Stops the scheduler, lets running requests finish, frees everything. */

@@ -28,7 +28,8 @@ BINV_F_SYNC = 1
 BINV_F_NO_LOOKAHEAD = 2
 
 # every exported entry point of include/binv.h
-EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_invert_noalloc", "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
+EXPORTS = ("binv_create", "binv_destroy", "binv_invert", "binv_invert_noalloc", "binv_sweep_steps", "binv_invert_host",
+           "binv_set_timing", "binv_get_timing", "binv_lookahead_cus",
            "binv_invert_mixed", "binv_residual", "binv_residual_matrix",
            "binv_batch_create", "binv_batch_destroy", "binv_batch_query", "binv_invert_batched",
            "binv_batch_tune", "binv_batch_shape", "binv_batch_residual",
@@ -107,6 +108,12 @@ def load_library():
     lib.binv_invert.restype = ctypes.c_int
     lib.binv_invert_noalloc.argtypes = lib.binv_invert.argtypes
     lib.binv_invert_noalloc.restype = ctypes.c_int
+    lib.binv_sweep_steps.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts), ctypes.c_int32,
+                                     ctypes.c_int32, P, P]
+    lib.binv_sweep_steps.restype = ctypes.c_int
+    lib.binv_invert_host.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.POINTER(_Opts), ctypes.c_size_t, P,
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.binv_invert_host.restype = ctypes.c_int
     lib.binv_set_timing.argtypes = [P, ctypes.c_uint32]
     lib.binv_set_timing.restype = ctypes.c_int
     lib.binv_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
@@ -255,7 +262,7 @@ def _stream_handle(torch, device):
 
 
 def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True,
-           pivot=False, _noalloc=False):
+           pivot=False, graph=False, _noalloc=False):
     """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
     inversion over the diagonal blocks `part` (or uniform blocks of `block`).
 
@@ -266,6 +273,8 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
              the current trailing update runs (bitwise identical results).
     pivot:   block-row pivoting (BINV_F_PIVOT): each pivot block's rows are
              chosen among all rows not yet used as pivots.
+    graph:   replay the call's launch sequence from a HIP graph cached in the
+             context (BINV_F_GRAPH; captured on the first call of a key).
     info:    optional int64 CUDA tensor of one element receiving the singular row.
     """
     import torch
@@ -288,6 +297,8 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     dev = A.device.index if A.device.index is not None else torch.cuda.current_device()
     ctx = ctx or default_context(dev)
     o, keep = _opts(part, block, sync, lookahead, pivot)
+    if graph:
+        o.flags |= BINV_F_GRAPH
     info_ptr = None
     if info is not None:
         if info.dtype != torch.int64 or not info.is_cuda or info.numel() < 1:
@@ -303,6 +314,58 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     del keep
     _check(st)
     return X
+
+
+def sweep_steps(W, p_begin, p_end=-1, part=None, block=None, sync=True, info=None, ctx=None, lookahead=True):
+    """Steps [p_begin, p_end) of the blockwise sweep in place on the float64
+    CUDA tensor W (binv_sweep_steps); W holds A before step 0 and the state a
+    previous range left otherwise.  Returns W."""
+    import torch
+
+    if W.dim() != 2 or W.shape[0] != W.shape[1] or W.dtype != torch.float64 or not W.is_cuda or W.stride(1) != 1:
+        raise ValueError("W must be a square row-major float64 CUDA tensor")
+    n = W.shape[0]
+    dev = W.device.index if W.device.index is not None else torch.cuda.current_device()
+    ctx = ctx or default_context(dev)
+    o, keep = _opts(part, block, sync, lookahead, False)
+    info_ptr = None
+    if info is not None:
+        if info.dtype != torch.int64 or not info.is_cuda or info.numel() < 1:
+            raise ValueError("info must be an int64 CUDA tensor with one element")
+        info_ptr = ctypes.c_void_p(info.data_ptr())
+    with torch.cuda.device(dev):
+        st = load_library().binv_sweep_steps(ctx.handle, n, ctypes.c_void_p(W.data_ptr()), max(W.stride(0), n, 1),
+                                             ctypes.byref(o), int(p_begin), int(p_end), _stream_handle(torch, dev),
+                                             info_ptr)
+    del keep
+    _check(st)
+    return W
+
+
+def invert_host(W, device_bytes, part=None, block=None, ctx=None, device=0):
+    """Invert the host matrix W (a C-contiguous float64 numpy array or CPU
+    tensor, pinned or not) in place out of core (binv_invert_host), using at
+    most device_bytes of device memory.  Returns W."""
+    import numpy as np
+    import torch
+
+    if isinstance(W, torch.Tensor):
+        if W.is_cuda or W.dtype != torch.float64 or W.dim() != 2 or W.shape[0] != W.shape[1] or W.stride(1) != 1:
+            raise ValueError("W must be a square row-major float64 host tensor")
+        ptr, n, ld = W.data_ptr(), W.shape[0], W.stride(0)
+    else:
+        if W.dtype != np.float64 or W.ndim != 2 or W.shape[0] != W.shape[1] or W.strides[1] != 8:
+            raise ValueError("W must be a square row-major float64 array")
+        ptr, n, ld = W.ctypes.data, W.shape[0], W.strides[0] // 8
+    ctx = ctx or default_context(device)
+    o, keep = _opts(part, block, False, True, False)
+    row = ctypes.c_int64(0)
+    with torch.cuda.device(ctx.device):
+        st = load_library().binv_invert_host(ctx.handle, n, ctypes.c_void_p(ptr), max(ld, n, 1), ctypes.byref(o),
+                                             int(device_bytes), _stream_handle(torch, ctx.device), ctypes.byref(row))
+    del keep
+    _check(st)
+    return W
 
 
 def invert_noalloc(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None):

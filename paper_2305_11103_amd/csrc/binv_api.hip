@@ -34,6 +34,21 @@ binv_status fail(binv_status st, const std::string& msg) {
 
 void binv::set_error(const std::string& msg) { g_err = msg; }
 
+size_t binv::ctx_device_bytes(const binv_ctx* c) {
+  size_t t = c->info.bytes;
+  for (const auto& L : c->lv)
+    for (int h = 0; h < 2; ++h) t += L.ct[h].bytes + L.r[h].bytes + L.p[h].bytes;
+  const binv::PivWork& P = c->piv;
+  for (const binv::DevBuf* d : {&P.T, &P.used, &P.chosen, &P.lvl[0], &P.lvl[1], &P.strip, &P.q, &P.g, &P.sel, &P.qs,
+                                &P.cs, &P.rj, &P.plan, &P.perm})
+    t += d->bytes;
+  for (const binv::DevBuf* d : {&c->mx_w32, &c->mx_ct32, &c->mx_r32, &c->mx_p32, &c->mx_p64a, &c->mx_p64b, &c->mx_res,
+                                &c->mx_xn, &c->mx_part, &c->mx_split_a, &c->mx_split_x, &c->mx_exps, &c->oo_rows,
+                                &c->oo_cols, &c->oo_slab[0], &c->oo_slab[1]})
+    t += d->bytes;
+  return t;
+}
+
 namespace {
 
 #define HIP_TRY(expr)                                                                      \
@@ -97,7 +112,7 @@ namespace {
 
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
                   hipStream_t s, long long* info, int64_t row0, bool lookahead, const double* src0 = nullptr,
-                  int64_t ldsrc0 = 0);
+                  int64_t ldsrc0 = 0, int p0 = 0, int p1 = -1);
 
 // Order of the sub-blocks of the nested sweep that inverts a pivot block
 // larger than one leaf (BINV_SUB_BLOCK may set 32, 64 or 128).
@@ -265,13 +280,19 @@ binv_status ensure_side(binv_ctx* c) {
 // src0 (lookahead only): where the caller's out-of-place copy into W takes
 // W from; block 0's pivot block is then read there, on the side stream,
 // beside that copy (the caller recorded ev_fork on s before the copy).
+// [p0, p1): the steps to run (p1 < 0: to the last block); W must hold the
+// state after step p0 - 1.  The lookahead never reaches past p1 - 1, so a
+// range ends with W holding exactly the state after step p1 - 1.
 binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, const std::vector<int32_t>& part,
                   hipStream_t s, long long* info, int64_t row0, bool lookahead, const double* src0,
-                  int64_t ldsrc0) {
+                  int64_t ldsrc0, int p0, int p1) {
   int bmax = 0;
   for (int32_t b : part) bmax = std::max(bmax, (int)b);
   const int k = (int)part.size();
-  lookahead = lookahead && level == 0 && k >= 2;
+  if (p1 < 0 || p1 > k) p1 = k;
+  if (p0 >= p1) return BINV_OK;
+  if (p0 > 0) src0 = nullptr;
+  lookahead = lookahead && level == 0 && p1 - p0 >= 2;
   Level& L = c->lv[level];
   binv_status st;
   for (int h = 0; h < (lookahead ? 2 : 1); ++h) {
@@ -284,7 +305,7 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
   for (int p = 0; p < k; ++p) off[p + 1] = off[p] + part[p];
 
   if (!lookahead) {
-    for (int p = 0; p < k; ++p) {
+    for (int p = p0; p < p1; ++p) {
       if ((st = block_pivot(c, level, W, ldw, off[p], part[p], 0, s, info, row0)) != BINV_OK) return st;
       if ((st = block_panels(c, level, n, W, ldw, off[p], part[p], 0, s)) != BINV_OK) return st;
       PhaseTimer t(c, level, BINV_PHASE_SCHUR, s);
@@ -311,18 +332,18 @@ binv_status sweep(binv_ctx* c, int level, int64_t n, double* W, int64_t ldw, con
     if ((st = block_pivot(c, level, src0, ldsrc0, off[0], part[0], 0, c->side, info, row0)) != BINV_OK) return st;
     HIP_TRY(hipEventRecord(c->ev_join, c->side));
     HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
-  } else if ((st = block_pivot(c, level, W, ldw, off[0], part[0], 0, s, info, row0)) != BINV_OK) {
+  } else if ((st = block_pivot(c, level, W, ldw, off[p0], part[p0], p0 & 1, s, info, row0)) != BINV_OK) {
     return st;
   }
-  if ((st = block_panels(c, level, n, W, ldw, off[0], part[0], 0, s)) != BINV_OK) return st;
+  if ((st = block_panels(c, level, n, W, ldw, off[p0], part[p0], p0 & 1, s)) != BINV_OK) return st;
   hipStream_t g = c->gemm;
   HIP_TRY(hipEventRecord(c->ev_fork, s));
   HIP_TRY(hipStreamWaitEvent(g, c->ev_fork, 0));
-  for (int p = 0; p < k; ++p) {
+  for (int p = p0; p < p1; ++p) {
     const int cur = p & 1;
     const double* Ct = (const double*)L.ct[cur].p;
     const double* R = (const double*)L.r[cur].p;
-    if (p + 1 == k) {
+    if (p + 1 == p1) {
       PhaseTimer t(c, level, BINV_PHASE_SCHUR, g);
       HIP_TRY(binv::launch_schur(Ct, n, R, n, W, ldw, n, off[p], part[p], 0, 0, 0, g, t.fl(), 0));
       break;
@@ -670,6 +691,16 @@ binv_status binv_destroy(binv_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+  for (auto& g : ctx->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  for (binv::DevBuf* d : {&ctx->oo_rows, &ctx->oo_cols, &ctx->oo_slab[0], &ctx->oo_slab[1]}) d->release();
+  for (hipStream_t st : ctx->oo_stream)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : ctx->oo_ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipSetDevice(prev);
   delete ctx;
   return BINV_OK;
@@ -843,6 +874,101 @@ binv_status sweep_f32(binv_ctx* c, int64_t n, const double* A, int64_t lda, doub
     o += b;
   }
   HIP_TRY(binv::launch_f32_to_f64(W, n, X, ldx, n, n, s));
+  return BINV_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Every workspace address of a context (what a captured graph bakes in).
+std::vector<const void*> workspace_addresses(const binv_ctx* c) {
+  std::vector<const void*> a;
+  a.push_back(c->info.p);
+  for (const auto& L : c->lv)
+    for (int h = 0; h < 2; ++h) {
+      a.push_back(L.ct[h].p);
+      a.push_back(L.r[h].p);
+      a.push_back(L.p[h].p);
+    }
+  const binv::PivWork& P = c->piv;
+  for (const binv::DevBuf* d : {&P.T, &P.used, &P.chosen, &P.lvl[0], &P.lvl[1], &P.strip, &P.q, &P.g, &P.sel, &P.qs,
+                                &P.cs, &P.rj, &P.plan, &P.perm})
+    a.push_back(d->p);
+  return a;
+}
+
+// binv_invert's work on stream s: clear the info word, copy A into X checking
+// that it is finite (in place: the check alone), then the sweep.
+binv_status invert_enqueue(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                           const std::vector<int32_t>& part, uint32_t flags, hipStream_t s, long long* info) {
+  const bool inplace = (A == X);
+  {
+    hipError_t e = binv::launch_zero_info(info, s);
+    if (e != hipSuccess) return fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e));
+  }
+  if (n == 0) return BINV_OK;
+  const bool look = !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2;
+  // out of place with the lookahead: block 0's pivot inversion reads A and
+  // runs on the side stream beside the copy of A into X
+  const bool early = look && !inplace && !(flags & BINV_F_PIVOT);
+  binv_status st;
+  if (early) {
+    if ((st = ensure_side(ctx)) != BINV_OK) return st;
+    hipError_t e = hipEventRecord(ctx->ev_fork, s);
+    if (e != hipSuccess) return fail(BINV_E_HIP, std::string("fork: ") + hipGetErrorString(e));
+  }
+  {
+    // the copy of A into X (out of place), checking that A is finite
+    PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
+    hipError_t e = binv::launch_copy2d_check(A, lda, X, ldx, n, n, info, s);
+    if (e != hipSuccess) return fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e));
+  }
+  if (flags & BINV_F_PIVOT) return sweep_pivoted(ctx, n, X, ldx, part, s, info, !(flags & BINV_F_NO_LOOKAHEAD));
+  return sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
+}
+
+// Capture invert_enqueue's launches into a graph kept in the context (at
+// most 16, the least recently used replaced).  Timing is off while capturing.
+binv_status invert_capture(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, double* X, int64_t ldx,
+                           const std::vector<int32_t>& part, uint32_t flags, long long* info,
+                           const std::vector<int64_t>& key) {
+  if (!ctx->cap) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+  if (ctx->graphs.size() >= 16) {
+    auto old = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                [](const binv_ctx::GraphEntry& a, const binv_ctx::GraphEntry& b) { return a.used < b.used; });
+    (void)hipGraphExecDestroy(old->exec);
+    (void)hipGraphDestroy(old->graph);
+    ctx->graphs.erase(old);
+  }
+  const uint32_t mask = ctx->timing_mask;
+  ctx->timing_mask = 0;
+  const std::vector<const void*> ws = workspace_addresses(ctx);
+  HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+  binv_status st = invert_enqueue(ctx, n, A, lda, X, ldx, part, flags, ctx->cap, info);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap, &g);
+  ctx->timing_mask = mask;
+  if (st != BINV_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(BINV_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (workspace_addresses(ctx) != ws) {
+    (void)hipGraphDestroy(g);
+    return fail(BINV_E_HIP, "the workspace grew while capturing");
+  }
+  binv_ctx::GraphEntry ent;
+  ent.key = key;
+  ent.ws = ws;
+  ent.graph = g;
+  hipError_t ie = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(BINV_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  }
+  ent.used = ++ctx->graph_clock;
+  ctx->graphs.push_back(ent);
   return BINV_OK;
 }
 
@@ -1094,31 +1220,39 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     if ((st = ctx->info.ensure(sizeof(long long))) != BINV_OK) goto out;
     info = (long long*)ctx->info.p;
   }
-  {
-    hipError_t e = binv::launch_zero_info(info, s);
-    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
+  if ((flags & BINV_F_GRAPH) && !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2) {
+    // the first capture of the two-stream lookahead schedule ended the process
+    // (a host-side crash during capture) and its cause is not known, so only
+    // the one-stream schedule is captured
+    st = fail(BINV_E_INVALID, "BINV_F_GRAPH needs BINV_F_NO_LOOKAHEAD (the lookahead schedule is not captured)");
+    goto out;
   }
-  if (n > 0) {
-    const bool look = !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2;
-    // out of place with the lookahead: block 0's pivot inversion reads A and
-    // runs on the side stream beside the copy of A into X
-    const bool early = look && !inplace && !(flags & BINV_F_PIVOT);
-    if (early) {
-      if ((st = ensure_side(ctx)) != BINV_OK) goto out;
-      hipError_t e = hipEventRecord(ctx->ev_fork, s);
-      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("fork: ") + hipGetErrorString(e)); goto out; }
+  if (flags & BINV_F_GRAPH) {
+    // replay the call's captured launch sequence; capture it after an eager
+    // run (which sizes the workspace) on first use, or when the workspace
+    // moved since
+    std::vector<int64_t> key = {n, lda, ldx, (int64_t)(uintptr_t)A, (int64_t)(uintptr_t)X,
+                                (int64_t)(uintptr_t)info, (int64_t)(flags & ~(BINV_F_SYNC | BINV_F_GRAPH))};
+    key.insert(key.end(), part.begin(), part.end());
+    binv_ctx::GraphEntry* hit = nullptr;
+    for (auto& g : ctx->graphs)
+      if (g.key == key) hit = &g;
+    if (hit && hit->ws != workspace_addresses(ctx)) {
+      (void)hipGraphExecDestroy(hit->exec);
+      (void)hipGraphDestroy(hit->graph);
+      ctx->graphs.erase(ctx->graphs.begin() + (hit - ctx->graphs.data()));
+      hit = nullptr;
     }
-    {
-      // the copy of A into X (out of place), checking that A is finite
-      PhaseTimer t(ctx, 0, BINV_PHASE_OTHER, s);
-      hipError_t e = binv::launch_copy2d_check(A, lda, X, ldx, n, n, info, s);
-      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e)); goto out; }
+    if (hit) {
+      hit->used = ++ctx->graph_clock;
+      hipError_t e = hipGraphLaunch(hit->exec, s);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e)); goto out; }
+    } else {
+      if ((st = invert_enqueue(ctx, n, A, lda, X, ldx, part, flags, s, info)) != BINV_OK) goto out;
+      if ((st = invert_capture(ctx, n, A, lda, X, ldx, part, flags, info, key)) != BINV_OK) goto out;
     }
-    if (flags & BINV_F_PIVOT)
-      st = sweep_pivoted(ctx, n, X, ldx, part, s, info, !(flags & BINV_F_NO_LOOKAHEAD));
-    else
-      st = sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
-    if (st != BINV_OK) goto out;
+  } else if ((st = invert_enqueue(ctx, n, A, lda, X, ldx, part, flags, s, info)) != BINV_OK) {
+    goto out;
   }
   if (flags & BINV_F_SYNC) {
     long long h = 0;
@@ -1127,6 +1261,163 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("sync: ") + hipGetErrorString(e)); goto out; }
     if (h < 0) st = fail(BINV_E_INVALID, "A holds a NaN or an infinity");
     if (h > 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
+  }
+out:
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+binv_status binv_sweep_steps(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, const binv_opts* opts,
+                             int32_t p_begin, int32_t p_end, void* stream, int64_t* d_info) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (n > 0 && !W) return fail(BINV_E_INVALID, "W is NULL");
+  if (n > 0 && ldw < n) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  const uint32_t flags = opts ? opts->flags : 0u;
+  if (flags & BINV_F_PIVOT)
+    return fail(BINV_E_INVALID, "binv_sweep_steps does not pivot across blocks (the row order would be state)");
+  std::vector<int32_t> part;
+  {
+    binv_status pst = parse_partition(n, opts, part);
+    if (pst != BINV_OK) return pst;
+  }
+  const int k = (int)part.size();
+  if (p_end < 0) p_end = k;
+  if (p_begin < 0 || p_begin > p_end || p_end > k)
+    return fail(BINV_E_INVALID, "step range outside 0 <= p_begin <= p_end <= " + std::to_string(k));
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  binv_status st = BINV_OK;
+  long long* info = (long long*)d_info;
+  if (!info) {
+    if ((st = ctx->info.ensure(sizeof(long long))) != BINV_OK) goto out;
+    info = (long long*)ctx->info.p;
+  }
+  if (p_begin == 0 || !d_info) {
+    // the caller's word starts at step 0; the internal one at every call
+    hipError_t e = binv::launch_zero_info(info, s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
+  }
+  if (n > 0 && p_end > p_begin) {
+    const bool look = !(flags & BINV_F_NO_LOOKAHEAD);
+    if ((st = sweep(ctx, 0, n, W, ldw, part, s, info, 0, look, nullptr, 0, p_begin, p_end)) != BINV_OK) goto out;
+  }
+  if (flags & BINV_F_SYNC) {
+    long long h = 0;
+    hipError_t e = hipMemcpyAsync(&h, info, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("sync: ") + hipGetErrorString(e)); goto out; }
+    if (h > 0) st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(h));
+  }
+out:
+  if (prev != ctx->device) (void)hipSetDevice(prev);
+  return st;
+}
+
+binv_status binv_invert_host(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, const binv_opts* opts,
+                             size_t device_bytes, void* stream, int64_t* singular_row) {
+  if (!ctx) return fail(BINV_E_INVALID, "ctx is NULL");
+  if (singular_row) *singular_row = 0;
+  if (n < 0) return fail(BINV_E_INVALID, "n < 0");
+  if (n > 0 && !W) return fail(BINV_E_INVALID, "W is NULL");
+  if (n > 0 && ldw < n) return fail(BINV_E_INVALID, "leading dimension smaller than n");
+  const uint32_t flags = opts ? opts->flags : 0u;
+  if (flags & BINV_F_PIVOT) return fail(BINV_E_INVALID, "binv_invert_host does not pivot across blocks");
+  std::vector<int32_t> part;
+  {
+    binv_status pst = parse_partition(n, opts, part);
+    if (pst != BINV_OK) return pst;
+  }
+  if (n == 0) return BINV_OK;
+  int bmax = 0;
+  for (int32_t b : part) bmax = std::max(bmax, (int)b);
+  if (bmax >= 2048) return fail(BINV_E_INVALID, "binv_invert_host needs diagonal blocks of order <= 2047");
+  const size_t d = sizeof(double), nb = (size_t)bmax * (size_t)n;
+  // fixed: the pivot rows, the column panel (as copied, then k-major), the
+  // row panel, the pivot inverse, the nested pivot sweep's panels, info
+  const size_t fixed = d * (4 * nb + (size_t)bmax * bmax + 4 * (64 * (size_t)bmax + 4096)) + 256;
+  const size_t per_row = 2 * d * (size_t)n;  // one row in each of the two slabs
+  if (device_bytes < fixed + per_row)
+    return fail(BINV_E_INVALID, "binv_invert_host: device_bytes below the " + std::to_string(fixed + per_row) +
+                                    " bytes one row slab needs for n = " + std::to_string(n));
+  int64_t h = (int64_t)std::min<size_t>((device_bytes - fixed) / per_row, (size_t)n);
+  if (h >= 128) h = h / 128 * 128;
+  int prev = 0;
+  HIP_TRY(hipGetDevice(&prev));
+  if (prev != ctx->device) HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  binv_status st = BINV_OK;
+  std::vector<int64_t> off(part.size() + 1, 0);
+  for (size_t p = 0; p < part.size(); ++p) off[p + 1] = off[p] + part[p];
+  Level& L = ctx->lv[0];
+  long long hinfo = 0;
+  {
+    struct { binv::DevBuf* b; size_t bytes; } want[] = {
+        {&ctx->oo_rows, d * nb}, {&ctx->oo_cols, d * nb}, {&L.ct[0], d * nb}, {&L.r[0], d * nb},
+        {&L.p[0], d * (size_t)bmax * bmax}, {&ctx->oo_slab[0], d * (size_t)h * n}, {&ctx->oo_slab[1], d * (size_t)h * n},
+        {&ctx->info, sizeof(long long)}};
+    for (auto& w : want)
+      if ((st = w.b->ensure(w.bytes)) != BINV_OK) goto out;
+  }
+  for (int i = 0; i < 2; ++i)
+    if (!ctx->oo_stream[i]) {
+      hipError_t e = hipStreamCreateWithFlags(&ctx->oo_stream[i], hipStreamNonBlocking);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+    }
+  for (int i = 0; i < 3; ++i)
+    if (!ctx->oo_ev[i]) {
+      hipError_t e = hipEventCreateWithFlags(&ctx->oo_ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
+    }
+  {
+    long long* info = (long long*)ctx->info.p;
+    double* rows = (double*)ctx->oo_rows.p;
+    double* cols = (double*)ctx->oo_cols.p;
+    double* Ct = (double*)L.ct[0].p;
+    double* R = (double*)L.r[0].p;
+    double* P = (double*)L.p[0].p;
+#define OOC_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) { st = fail(BINV_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); goto out; } \
+  } while (0)
+    OOC_TRY(binv::launch_zero_info(info, s));
+    for (size_t p = 0; p < part.size(); ++p) {
+      const int64_t o = off[p];
+      const int b = part[p];
+      // block p's rows and its column panel, as the last step left them on the host
+      OOC_TRY(hipMemcpy2DAsync(rows, d * n, W + o * ldw, d * ldw, d * n, b, hipMemcpyHostToDevice, s));
+      OOC_TRY(hipMemcpy2DAsync(cols, d * b, W + o, d * ldw, d * b, n, hipMemcpyHostToDevice, s));
+      OOC_TRY(binv::launch_col_save(cols, b, n, 0, b, Ct, n, s));
+      if ((st = invert_pivot(ctx, 0, rows + o, n, b, P, s, info, o)) != BINV_OK) goto out;
+      OOC_TRY(binv::launch_row_panel_rows(P, b, rows, n, n, o, b, R, n, s));
+      // every row slab: in, trailing update (block p's rows take R), out;
+      // the two slab streams alternate so copies overlap the other's update
+      OOC_TRY(hipEventRecord(ctx->oo_ev[2], s));
+      int64_t j = 0;
+      for (int64_t r0 = 0; r0 < n; r0 += h, ++j) {
+        const int64_t hr = std::min<int64_t>(h, n - r0);
+        hipStream_t ss = ctx->oo_stream[j & 1];
+        double* S = (double*)ctx->oo_slab[j & 1].p;
+        OOC_TRY(hipStreamWaitEvent(ss, ctx->oo_ev[2], 0));
+        OOC_TRY(hipMemcpy2DAsync(S, d * n, W + r0 * ldw, d * ldw, d * n, hr, hipMemcpyHostToDevice, ss));
+        OOC_TRY(binv::launch_schur_rows(Ct, n, R, n, S, n, r0, hr, n, o, b, ss));
+        OOC_TRY(hipMemcpy2DAsync(W + r0 * ldw, d * ldw, S, d * n, d * n, hr, hipMemcpyDeviceToHost, ss));
+      }
+      for (int i = 0; i < 2; ++i) {
+        OOC_TRY(hipEventRecord(ctx->oo_ev[i], ctx->oo_stream[i]));
+        OOC_TRY(hipStreamWaitEvent(s, ctx->oo_ev[i], 0));
+      }
+    }
+    OOC_TRY(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    OOC_TRY(hipStreamSynchronize(s));
+#undef OOC_TRY
+  }
+  if (hinfo != 0) {
+    if (singular_row) *singular_row = hinfo;
+    st = fail(BINV_E_SINGULAR, "exactly-zero pivot at row " + std::to_string(hinfo));
   }
 out:
   if (prev != ctx->device) (void)hipSetDevice(prev);

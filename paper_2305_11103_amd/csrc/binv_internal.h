@@ -113,6 +113,10 @@ hipError_t launch_row_panel(const double* P, int64_t ldp, const double* W, int64
 hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw, int64_t n,
                         int64_t o, int b, int region, int64_t qo, int qb, hipStream_t s, double* flops,
                         int part = 0, double split = 1.0, const ColSave* cs = nullptr);
+hipError_t launch_row_panel_rows(const double* P, int64_t ldp, const double* Wp, int64_t ldw, int64_t n, int64_t o,
+                                 int b, double* R, int64_t ldr, hipStream_t s);
+hipError_t launch_schur_rows(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* S, int64_t lds,
+                             int64_t r0, int64_t h, int64_t n, int64_t o, int b, hipStream_t s);
 hipError_t launch_schur_leaf(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* W, int64_t ldw,
                              const double* Win, int64_t ldwin, int64_t n, int64_t o, int b, const SchurLeafArgs& a,
                              hipStream_t s);
@@ -311,6 +315,23 @@ struct binv_ctx {
   std::vector<hipEvent_t> ev_free;
   struct Pending { int phase; hipEvent_t a, b; double flops; };
   std::vector<Pending> pending;
+  // binv_invert's launch sequences captured as HIP graphs (BINV_F_GRAPH),
+  // keyed by the call; ws holds the workspace addresses baked into the graph
+  struct GraphEntry {
+    std::vector<int64_t> key;
+    std::vector<const void*> ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t cap = nullptr;
+  // out-of-core inversion (binv_invert_host): the pivot rows and the column
+  // panel as copied from the host, two row slabs, and the slabs' streams
+  binv::DevBuf oo_rows, oo_cols, oo_slab[2];
+  hipStream_t oo_stream[2] = {nullptr, nullptr};
+  hipEvent_t oo_ev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace binv {
@@ -353,5 +374,8 @@ struct PhaseTimer {
 
 constexpr int kLeafMax = 128;   // largest pivot block the register leaf kernel holds
 constexpr int kSubBlock = 64;   // sub-block order of the nested sweep of a larger pivot block
+
+// Device bytes a context's workspace holds (binv_api.hip).
+size_t ctx_device_bytes(const binv_ctx* c);
 
 }  // namespace binv

@@ -241,6 +241,8 @@ template <int RPL, int CPW, int NWV>
 __global__ void __launch_bounds__(64 * NWV) k_leaf_inverse(const double* __restrict__ A, int64_t lda,
                                                            double* __restrict__ P, int64_t ldp, int b,
                                                            int64_t row0, long long* info) {
+  // a leaf is on the pivot chain, which gates the next step
+  __builtin_amdgcn_s_setprio(3);
   leaf_body<RPL, CPW, NWV>(A, lda, P, ldp, b, row0, info);
 }
 
@@ -951,6 +953,38 @@ hipError_t launch_schur(const double* Ct, int64_t ldc, const double* R, int64_t 
   return launch_step<MODE_SCHUR, 64, 64, true>(g, s, region, qo, qb, flops, part, split, cs);
 }
 
+// The row panel from the pivot rows held on their own (Wp: b x n, ld ldw):
+// launch_row_panel's launch with its operand B at Wp instead of W + o ldw.
+hipError_t launch_row_panel_rows(const double* P, int64_t ldp, const double* Wp, int64_t ldw, int64_t n, int64_t o,
+                                 int b, double* R, int64_t ldr, hipStream_t s) {
+  StepArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = P; g.lda = ldp;
+  g.B = Wp; g.ldb = ldw;
+  g.W = R; g.ldw = ldr;
+  g.R = P; g.ldr = ldp;
+  g.M = b; g.N = n; g.K = b; g.o = o; g.b = b; g.oc = o;
+  if (b >= 128 && n >= 2048) return launch_step<MODE_ROW, 64, 128, false, 2, 4>(g, s, 0, 0, 0, nullptr);
+  return launch_step<MODE_ROW, 64, 64, false>(g, s, 0, 0, 0, nullptr);
+}
+
+// The trailing update of rows [r0, r0 + h) held on their own (S: h x n, ld
+// lds, in place), with the block's saved column panel Ct (b x n, k-major, ld
+// ldc, global rows) and row panel R: rows of block p among them take R.
+hipError_t launch_schur_rows(const double* Ct, int64_t ldc, const double* R, int64_t ldr, double* S, int64_t lds,
+                             int64_t r0, int64_t h, int64_t n, int64_t o, int b, hipStream_t s) {
+  StepArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = Ct + r0; g.lda = ldc;
+  g.B = R; g.ldb = ldr;
+  g.W = S; g.ldw = lds;
+  g.Win = S; g.ldwin = lds;
+  g.R = R; g.ldr = ldr;
+  g.M = h; g.N = n; g.K = b; g.o = o - r0; g.b = b; g.oc = o;
+  if (schur_tile(n) == 128) return launch_step<MODE_SCHUR, 128, 128, true, 4, 2>(g, s, 0, 0, 0, nullptr);
+  return launch_step<MODE_SCHUR, 64, 64, true>(g, s, 0, 0, 0, nullptr);
+}
+
 // The fused nested step: Schur update of step p (block [o, o+b)) of Win
 // (ld ldwin) into W (ld ldw; Win == W in place), n x n with n < 2048, with
 // the leaf of block q = [qo, qo+qb) (qo a multiple of 64, qb <= 64) into
@@ -1205,6 +1239,9 @@ __device__ __forceinline__ int tourn_search(const double (&x)[RPL], const bool (
 // One tournament node per workgroup: 4 waves, lane l holding candidates
 // l + 64 h (h < 4), wave v holding strip columns [16 v, 16 v + 16).
 __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
+  // the selection gates the next step's row panel and runs beside the
+  // trailing update: its waves issue ahead of the update's on shared CUs
+  __builtin_amdgcn_s_setprio(3);
   constexpr int RPL = kTournRows / 64, CPW = 16;
   __shared__ int cand[kTournRows];
   __shared__ int wcount[4];
@@ -1212,7 +1249,7 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
   __shared__ int s_r[2];
   __shared__ double s_pv[2];
   __shared__ int picks[64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t node = blockIdx.x;
 
   // candidates, in order: a leaf's rows not yet chosen, or the children's picks

@@ -64,7 +64,8 @@ struct Request {
   std::vector<double> hostA;  // staging until admission
   double* dA = nullptr;       // device copy of A (server-owned)
   double* dX = nullptr;       // device result
-  size_t bytes = 0;           // device bytes charged to the budget
+  size_t blk = 0;             // bytes of the request's device block (A then X)
+  size_t ws = 0;              // workspace reserved for it until it finishes
   bool on_device = false;     // dA/dX already allocated and charged at submit
   bool fp32_start = false;    // the sweep ran in FP32 (mixed request)
   ReqState state = Q_QUEUED;
@@ -74,16 +75,37 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
 };
 
-// device bytes a request needs while in flight
-size_t request_bytes(int64_t n, int prec) {
-  const size_t nn = (size_t)n * (size_t)n;
-  size_t b = 16 * nn;                                       // A and X
-  if (n > kSmallMax) {
-    const int64_t blk = std::min<int64_t>(512, n);
-    b += 4 * 8 * (size_t)blk * (size_t)n + 8 * (size_t)blk * blk * 2;  // panels (two sets) + pivots
-    if (prec == BINV_PREC_MIXED_F32) b += 20 * nn;          // FP32 copy, residual, next iterate
-  }
-  return b;
+// Allocation class of a request block: 1/8-octave steps, at least 64 KiB.
+size_t size_class(size_t bytes) {
+  size_t c = 64 << 10;
+  if (bytes <= c) return c;
+  int e = 63 - __builtin_clzll((unsigned long long)bytes);  // 2^e <= bytes < 2^(e+1)
+  const size_t step = (size_t)1 << (e - 3);
+  return (bytes + step - 1) / step * step;
+}
+
+// Device bytes of a request's block (A then X).
+size_t block_bytes(int64_t n) { return size_class(2 * sizeof(double) * std::max<size_t>((size_t)n * (size_t)n, 1)); }
+
+// Diagonal-block order the workers use for a request of order n.
+int worker_block(int64_t n) { return n >= 2048 ? 512 : (n >= 512 ? 256 : 128); }
+
+// Upper bound of the workspace a request makes the server hold while it runs:
+// for orders <= kSmallMax its share of a round's buffers (packed copies of A
+// and X, two m x m refinement buffers, the tables); above that what a worker
+// context's binv_invert_mixed can grow to for it: the sweep's panels (two
+// sets under the lookahead) and the nested pivot sweep's, the residual and
+// next iterate, the compensated residual's split operands, and the FP32
+// working copy and panels when it starts from the FP32 sweep.
+size_t workspace_bytes(int64_t n, bool fp32_start) {
+  const size_t nn = (size_t)n * (size_t)n, d = sizeof(double);
+  if (n <= kSmallMax) return 4 * d * nn + 64;
+  const size_t b = (size_t)worker_block(n), sets = n >= kBigN ? 2 : 1;
+  size_t w = sets * d * (2 * b * (size_t)n + b * b);  // level-0 panels and pivot inverse
+  w += 2 * d * (2 * 64 * b + 64 * 64);               // the nested pivot sweep's panels
+  w += d * (nn + nn + 1025) + 2 * d * (2 * nn) + 2 * sizeof(int) * (size_t)n + d;  // res, xn, parts, splits, info
+  if (fp32_start) w += sizeof(float) * (nn + 2 * b * (size_t)n + b * b) + 2 * d * b * b;
+  return w + (1 << 20);  // allocation granularity
 }
 
 }  // namespace
@@ -124,6 +146,13 @@ struct binv_server {
   // worker stream never reads a block before its input has landed
   hipStream_t cstream = nullptr;
   binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo, rwork, rtarget, rrho, rsteps;
+  // Accounting: `used` counts every byte the server holds on the device or
+  // has promised: blocks of admitted requests, blocks kept in the cache,
+  // workspace held by the worker contexts (ws_held) and by the round buffers
+  // (round_held), and the workspace reserved for requests still running.
+  size_t ws_held[kMaxWorkers] = {0};
+  bool worker_busy[kMaxWorkers] = {false};
+  size_t round_held = 0;
   // statistics
   std::atomic<int64_t> completed{0};
 };
@@ -150,71 +179,134 @@ hipError_t copy_sync(binv_server* s, void* dst, const void* src, size_t bytes, h
   return e;
 }
 
-// Allocation class of a request block: 1/8-octave steps, at least 64 KiB.
-size_t size_class(size_t bytes) {
-  size_t c = 64 << 10;
-  if (bytes <= c) return c;
-  int e = 63 - __builtin_clzll((unsigned long long)bytes);  // 2^e <= bytes < 2^(e+1)
-  const size_t step = (size_t)1 << (e - 3);
-  return (bytes + step - 1) / step * step;
+// Whether the cache holds a block of class c.
+bool pool_has(binv_server* s, size_t c) {
+  std::lock_guard<std::mutex> g(s->pool_mu);
+  return s->pool.find(c) != s->pool.end();
 }
 
-void* pool_get(binv_server* s, size_t bytes) {
-  const size_t c = size_class(bytes);
-  {
-    std::lock_guard<std::mutex> g(s->pool_mu);
-    auto it = s->pool.find(c);
-    if (it != s->pool.end()) {
-      void* p = it->second;
-      s->pool.erase(it);
-      s->pooled -= c;
-      return p;
-    }
-  }
+// A block of class c from the cache (already counted in `used`), or NULL.
+void* pool_take(binv_server* s, size_t c) {
+  std::lock_guard<std::mutex> g(s->pool_mu);
+  auto it = s->pool.find(c);
+  if (it == s->pool.end()) return nullptr;
+  void* p = it->second;
+  s->pool.erase(it);
+  s->pooled -= c;
+  return p;
+}
+
+// Free one cached block of a class other than `keep` (mu held); false if
+// none is left.  hipFree waits for the device, so this runs only when a
+// request could not be admitted otherwise.
+bool pool_evict_locked(binv_server* s, size_t keep) {
   void* p = nullptr;
-  if (hipMalloc(&p, c) == hipSuccess) return p;
-  (void)hipGetLastError();
-  // out of device memory: give the cached blocks back and try once more
-  std::multimap<size_t, void*> drop;
+  size_t c = 0;
   {
     std::lock_guard<std::mutex> g(s->pool_mu);
-    drop.swap(s->pool);
-    s->pooled = 0;
+    for (auto it = s->pool.begin(); it != s->pool.end(); ++it)
+      if (it->first != keep) {
+        p = it->second;
+        c = it->first;
+        s->pool.erase(it);
+        s->pooled -= c;
+        break;
+      }
   }
-  for (auto& kv : drop) (void)hipFree(kv.second);
-  if (hipMalloc(&p, c) == hipSuccess) return p;
-  (void)hipGetLastError();
-  return nullptr;
-}
-
-// Return a block to the cache; the cache never holds more than a quarter of
-// the budget (so the server's device memory stays within 1.25 x budget).
-void pool_put(binv_server* s, void* p, size_t bytes) {
-  if (!p) return;
-  const size_t c = size_class(bytes);
-  {
-    std::lock_guard<std::mutex> g(s->pool_mu);
-    if (s->pooled + c <= s->budget / 4) {
-      s->pool.emplace(c, p);
-      s->pooled += c;
-      return;
-    }
-  }
-  (void)hipFree(p);
-}
-
-// A and X of one request share one block: A first, X after it.
-bool request_alloc(binv_server* s, Request* r) {
-  const size_t nn = std::max<size_t>((size_t)r->n * (size_t)r->n, 1);
-  double* p = (double*)pool_get(s, 2 * sizeof(double) * nn);
   if (!p) return false;
+  (void)hipFree(p);
+  s->used -= c;
+  return true;
+}
+
+// Release the workspace of idle worker contexts (mu held), the largest
+// first, until `need` more bytes fit; false if that is not enough.
+bool trim_workers_locked(binv_server* s, size_t need) {
+  while (s->used + need > s->budget) {
+    int best = -1;
+    for (int w = 0; w < s->nworkers; ++w)
+      if (!s->worker_busy[w] && s->ws_held[w] > 0 && (best < 0 || s->ws_held[w] > s->ws_held[best])) best = w;
+    if (best < 0) return false;
+    binv_ctx* c = s->wctx[best];
+    for (auto& L : c->lv)
+      for (int h = 0; h < 2; ++h) {
+        L.ct[h].release();
+        L.r[h].release();
+        L.p[h].release();
+      }
+    c->info.release();
+    c->piv.release();
+    for (binv::DevBuf* d : {&c->mx_w32, &c->mx_ct32, &c->mx_r32, &c->mx_p32, &c->mx_p64a, &c->mx_p64b, &c->mx_res,
+                            &c->mx_xn, &c->mx_part, &c->mx_split_a, &c->mx_split_x, &c->mx_exps})
+      d->release();
+    s->used -= s->ws_held[best];
+    s->ws_held[best] = binv::ctx_device_bytes(c);  // 0
+    s->used += s->ws_held[best];
+  }
+  return true;
+}
+
+// Make room for a request (mu held): its workspace reservation and, unless
+// the cache has a block of its class, a new block; cached blocks of other
+// classes and idle workers' workspace are released when that is the only way,
+// and, called from the scheduler thread (the only one that uses them), the
+// small-request round buffers too.
+bool make_room_locked(binv_server* s, Request* r, bool scheduler) {
+  const size_t need = r->ws + (pool_has(s, r->blk) ? 0 : r->blk);
+  while (s->used + need > s->budget)
+    if (!pool_evict_locked(s, r->blk)) break;
+  if (s->used + need > s->budget) (void)trim_workers_locked(s, need);
+  if (s->used + need > s->budget && scheduler && s->round_held > 0) {
+    for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork, &s->rtarget,
+                            &s->rrho, &s->rsteps})
+      d->release();
+    s->used -= s->round_held;
+    s->round_held = 0;
+  }
+  return s->used + need <= s->budget;
+}
+
+// A and X of one request share one block: A first, X after it.  Charges
+// the block (unless it comes from the cache, where it is already counted)
+// and the workspace reservation (mu held).
+bool request_alloc_locked(binv_server* s, Request* r) {
+  const size_t nn = std::max<size_t>((size_t)r->n * (size_t)r->n, 1);
+  double* p = (double*)pool_take(s, r->blk);
+  if (!p) {
+    if (hipMalloc((void**)&p, r->blk) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    s->used += r->blk;
+  }
+  s->used += r->ws;
+  s->peak = std::max(s->peak, s->used);
   r->dA = p;
   r->dX = p + nn;
   return true;
 }
 
-void request_release(binv_server* s, Request* r) {
-  if (r->dA) pool_put(s, r->dA, 2 * sizeof(double) * std::max<size_t>((size_t)r->n * (size_t)r->n, 1));
+// The request's block back to the cache, which keeps at most a quarter of the
+// budget in blocks (still counted in `used`); otherwise it is freed.  Any
+// workspace reservation left is released (mu held).
+void request_release_locked(binv_server* s, Request* r) {
+  if (r->dA) {
+    bool kept = false;
+    {
+      std::lock_guard<std::mutex> g(s->pool_mu);
+      if (s->pooled + r->blk <= s->budget / 4) {
+        s->pool.emplace(r->blk, (void*)r->dA);
+        s->pooled += r->blk;
+        kept = true;
+      }
+    }
+    if (!kept) {
+      (void)hipFree(r->dA);
+      s->used -= r->blk;
+    }
+  }
+  s->used -= r->ws;
+  r->ws = 0;
   r->dA = r->dX = nullptr;
 }
 
@@ -245,18 +337,16 @@ void admit_locked(binv_server* s) {
       route_locked(s, r);
       continue;
     }
-    if (s->used + r->bytes > s->budget) break;  // wait until results are collected
+    if (!make_room_locked(s, r, true)) break;  // wait until results are collected
     const size_t nn = (size_t)r->n * (size_t)r->n;
-    if (!request_alloc(s, r)) break;
+    if (!request_alloc_locked(s, r)) break;
     if (copy_sync(s, r->dA, r->hostA.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipGetLastError();
-      request_release(s, r);
+      request_release_locked(s, r);
       break;
     }
     std::vector<double>().swap(r->hostA);
     s->queue.pop_front();
-    s->used += r->bytes;
-    s->peak = std::max(s->peak, s->used);
     s->inflight++;
     r->state = Q_ADMITTED;
     r->t_admit = now_s();
@@ -346,6 +436,23 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
       err = std::string("small round: ") + hipGetErrorString(he);
     }
   }
+  {
+    // the round buffers are charged as they grew; the requests' workspace
+    // reservations end with the round
+    size_t held = 0;
+    for (const binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork,
+                                  &s->rtarget, &s->rrho, &s->rsteps})
+      held += d->bytes;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->used += held;
+    s->used -= s->round_held;
+    s->round_held = held;
+    for (int64_t i = 0; i < cnt; ++i) {
+      s->used -= reqs[i]->ws;
+      reqs[i]->ws = 0;
+    }
+    s->peak = std::max(s->peak, s->used);
+  }
   for (int64_t i = 0; i < cnt; ++i) {
     std::memset(&reqs[i]->info, 0, sizeof(binv_info));
     reqs[i]->info.rho = hrho[i];
@@ -399,6 +506,7 @@ void worker_main(binv_server* s, int w) {
       r = q.front();
       q.pop_front();
       r->state = Q_RUNNING;
+      s->worker_busy[w] = true;
     }
     binv_status e;
     std::memset(&r->info, 0, sizeof(binv_info));
@@ -426,6 +534,18 @@ void worker_main(binv_server* s, int w) {
     // request's own target is reported as not converged
     if (e == BINV_E_NOCONVERGE && r->info.converged) e = BINV_OK;
     r->fp32_start = fp32_start;
+    {
+      // the context keeps the workspace it grew to: charged from now on in
+      // place of the request's reservation
+      const size_t held = binv::ctx_device_bytes(s->wctx[w]);
+      std::lock_guard<std::mutex> g(s->mu);
+      s->used += held;
+      s->used -= s->ws_held[w] + r->ws;
+      s->ws_held[w] = held;
+      r->ws = 0;
+      s->worker_busy[w] = false;
+      s->peak = std::max(s->peak, s->used);
+    }
     finish(s, r, e, e == BINV_OK ? "" : binv_last_error());
   }
   if (st) (void)hipStreamDestroy(st);
@@ -487,8 +607,11 @@ binv_status binv_submit(binv_server* s, int64_t n, const double* A, int a_is_dev
   r->n = n;
   r->prec = prec;
   r->target = target > 0 ? target : 1e-10;
-  r->bytes = request_bytes(n, prec);
-  if (r->bytes > s->budget) {
+  const bool fp32_start = prec == BINV_PREC_MIXED_F32 &&
+                          ((s->flags & BINV_SERVER_STRICT_PRECISION) || r->target >= kFp32Reach);
+  r->blk = block_bytes(n);
+  r->ws = workspace_bytes(n, fp32_start);
+  if (r->blk + r->ws > s->budget) {
     delete r;
     return sfail(BINV_E_NOMEM, "request alone exceeds the server's HBM budget");
   }
@@ -499,22 +622,21 @@ binv_status binv_submit(binv_server* s, int64_t n, const double* A, int a_is_dev
     bool reserved = false;
     {
       std::lock_guard<std::mutex> g(s->mu);
-      if (s->used + r->bytes <= s->budget) {
-        s->used += r->bytes;
-        s->peak = std::max(s->peak, s->used);
-        reserved = true;
-      }
+      // only when the queue is empty: a device input must not overtake
+      // requests waiting for room
+      reserved = s->queue.empty() && make_room_locked(s, r, false) && request_alloc_locked(s, r);
     }
     if (reserved) {
-      hipError_t e = request_alloc(s, r) ? hipSuccess : hipErrorOutOfMemory;
-      if (e == hipSuccess) e = copy_sync(s, r->dA, A, sizeof(double) * nn, hipMemcpyDeviceToDevice);
+      hipError_t e = copy_sync(s, r->dA, A, sizeof(double) * nn, hipMemcpyDeviceToDevice);
       if (e == hipSuccess) {
         r->on_device = true;
       } else {
         (void)hipGetLastError();
-        request_release(s, r);
         std::lock_guard<std::mutex> g(s->mu);
-        s->used -= r->bytes;
+        request_release_locked(s, r);
+        const bool fp32 = prec == BINV_PREC_MIXED_F32 &&
+                          ((s->flags & BINV_SERVER_STRICT_PRECISION) || r->target >= kFp32Reach);
+        r->ws = workspace_bytes(n, fp32);
       }
     }
   }
@@ -569,10 +691,9 @@ binv_status binv_poll(binv_server* s, uint64_t ticket, double* X, int x_is_devic
     times->queue_ms = (r->t_admit - r->t_submit) * 1e3;
     times->total_ms = (r->t_done - r->t_submit) * 1e3;
   }
-  request_release(s, r);
   {
     std::lock_guard<std::mutex> g(s->mu);
-    s->used -= r->bytes;
+    request_release_locked(s, r);
     s->cv.notify_all();
   }
   delete r;

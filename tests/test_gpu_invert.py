@@ -250,10 +250,10 @@ def test_timing_reports_flops(gpu):
 
 def test_full_size_bench_configuration(gpu):
     """The benchmark's own configuration (n = 8192, 16 x 16 grid of 512-blocks,
-    SPD Q diag(s) Q^T with cond 1e4, lookahead schedule), checked through
-    properties that hold at any size: the oracle's compensated residual on 48
-    sampled rows, and the symmetry of the inverse of a symmetric matrix on the
-    sampled rows and columns."""
+    SPD Q diag(s) Q^T with cond 1e4, lookahead schedule): the oracle's
+    compensated residual on 48 sampled rows, the symmetry of the inverse of a
+    symmetric matrix on the sampled rows and columns, and every element
+    against the oracle's Gauss-Jordan inverse within 64 n u cond max|X|."""
     import torch
     from paper_2305_11103_amd import binv
     n = 8192
@@ -268,6 +268,11 @@ def test_full_size_bench_configuration(gpu):
     # the inverse of a symmetric matrix is symmetric: rounding-level asymmetry only
     asym = np.max(np.abs(Xn[rows][:, rows] - Xn[rows][:, rows].T)) / np.max(np.abs(Xn))
     assert asym <= 1e-9
+    # element by element against Gauss-Jordan with partial pivoting on the
+    # whole matrix (the oracle on the host's cores, about half a minute)
+    print("full-size elementwise check against the oracle", flush=True)
+    Xo = oracle.gj_inverse(An)
+    assert np.max(np.abs(Xn - Xo)) <= 64 * n * U * 1e4 * np.max(np.abs(Xo))
 
 
 @pytest.mark.parametrize("inplace,where", [(False, (0, 0)), (False, (699, 3)), (True, (5, 698)), (True, (699, 699))])
@@ -302,3 +307,72 @@ def test_non_finite_with_a_zero_pivot_reports_invalid(gpu):
     binv.invert(torch.from_numpy(A_np).cuda(), part=[64] * 4, sync=False, info=info)
     torch.cuda.synchronize()
     assert int(info.item()) == -1
+
+
+_LOOKAHEAD_CAPTURE_OFF = ("capture of the two-stream lookahead schedule ended the test process with a host "
+                          "segmentation fault on its first run (no GPU fault); the cause is not found, so that "
+                          "path is switched off (BINV_F_GRAPH needs BINV_F_NO_LOOKAHEAD)")
+
+
+@pytest.mark.parametrize("n,part,look", [
+    pytest.param(256, [64] * 4, True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF)),
+    pytest.param(1536, [512, 512, 512], True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF)),
+    (700, [300, 400], False), (256, [64] * 4, False), (1536, [512, 512, 512], False),
+    pytest.param(1000, [200, 300, 500], True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF))])
+def test_graph_replays_match_eager_every_time(gpu, n, part, look):
+    """BINV_F_GRAPH: the first call runs eagerly and captures; every later
+    call replays.  Each replay, with other eager work and synchronizations in
+    between, equals the eager result bitwise, also after A's contents change
+    under the same pointer (the replay reads A afresh)."""
+    import torch
+    from paper_2305_11103_amd import binv
+    A1 = wl.diag_dominant(n, wl.stream_seed(1, 120 + n))
+    A2 = wl.spd_haar(n, wl.stream_seed(2, 121 + n), 1e2)
+    A = torch.from_numpy(A1).cuda()
+    X = torch.empty_like(A)
+    other = torch.from_numpy(wl.diag_dominant(300, 5)).cuda()
+    ref1 = binv.invert(A, part=part, lookahead=look)
+    for i in range(4):
+        binv.invert(A, part=part, out=X, lookahead=look, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref1), i
+        binv.invert(other, block=128)  # eager work between replays
+        torch.cuda.synchronize()
+    A.copy_(torch.from_numpy(A2).cuda())
+    ref2 = binv.invert(A, part=part, lookahead=look)
+    for i in range(3):
+        X.fill_(7.0)
+        binv.invert(A, part=part, out=X, lookahead=look, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref2), i
+    _check(A2, X.cpu().numpy(), kappa=1e2)
+
+
+def test_graph_singular_and_non_finite_through_replays(gpu):
+    import torch
+    from paper_2305_11103_amd import binv
+    n, part = 256, [64] * 4
+    A_np = wl.diag_dominant(n, 33)
+    A = torch.from_numpy(A_np).cuda()
+    X = torch.empty_like(A)
+    # graph capture needs the one-stream schedule (rejected before any launch)
+    with pytest.raises(binv.BinvError) as e:
+        binv.invert(A, part=part, out=X, graph=True)
+    assert e.value.status == binv.BINV_E_INVALID
+    kw = dict(part=part, out=X, graph=True, lookahead=False)
+    binv.invert(A, **kw)
+    binv.invert(A, **kw)
+    bad = A_np.copy()
+    bad[:, 70] = 0.0
+    A.copy_(torch.from_numpy(bad).cuda())
+    with pytest.raises(binv.SingularError):
+        binv.invert(A, **kw)
+    bad[3, 3] = np.nan
+    A.copy_(torch.from_numpy(bad).cuda())
+    with pytest.raises(binv.BinvError) as e:
+        binv.invert(A, **kw)
+    assert e.value.status == binv.BINV_E_INVALID
+    A.copy_(torch.from_numpy(A_np).cuda())
+    binv.invert(A, **kw)
+    torch.cuda.synchronize()
+    _check(A_np, X.cpu().numpy())

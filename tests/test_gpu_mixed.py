@@ -109,21 +109,31 @@ def test_sampled_check_refines_when_the_sweep_misses(gpu):
     assert oracle.residual_stats(A, X.cpu().numpy())["rho"] <= 1e-10
 
 
-def test_full_size_mixed_configuration(gpu):
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_full_size_mixed_configuration(gpu, cond):
     """The mixed-precision workload's size (n = 16384, 32 x 32 grid of
-    512-blocks, U diag(s) V^T with cond 1e2): the result meets the target on
-    the oracle's compensated residual over sampled rows."""
+    512-blocks, U diag(s) V^T) at every cond, with block-row pivoting in the
+    FP64 sweep: the device reports convergence by its full compensated
+    residual (every row), binv_residual recomputes that residual to the same
+    value, and the oracle's compensated residual over 64 sampled rows agrees
+    and meets the target."""
     import torch
     from paper_2305_11103_amd import binv
     n = 16384
-    A = wl.general_haar_device(n, wl.stream_seed(3, 0), 1e2, "cuda").contiguous()
-    X, info = binv.invert_mixed(A, block=512)
+    print(f"mixed full size cond={cond:g}", flush=True)
+    A = wl.general_haar_device(n, wl.stream_seed(3, {1e2: 0, 1e4: 1, 1e6: 2}[cond]), cond, "cuda").contiguous()
+    X, info = binv.invert_mixed(A, block=512, pivot=True)
     torch.cuda.synchronize()
-    assert info["converged"]
-    rows = np.sort(np.random.default_rng(8).choice(n, 12, replace=False))
+    assert info["converged"] and info["rho"] <= 1e-10
+    rho_full = binv.residual(A, X, compensated=True)
+    assert rho_full == info["rho"]
+    rows = np.sort(np.random.default_rng(8).choice(n, 64, replace=False))
     An = A.cpu().numpy()
     Xn = X.cpu().numpy()
-    assert oracle.residual_stats(An, Xn, rows)["rho"] <= 1e-10
+    rho_rows = oracle.residual_stats(An, Xn, rows)["rho"]
+    assert rho_rows <= 1e-10
+    # the sample and the full residual measure the same spread-out error
+    assert 0.5 * rho_full <= rho_rows <= 2.0 * rho_full
 
 
 def test_mixed_degenerate_orders(gpu):
