@@ -788,14 +788,13 @@ def bench_serve(args):
         binv.invert(A, block=blk(n), out=X, ctx=ctx, lookahead=n >= 4096)
         torch.cuda.synchronize()
         t_plain += time.perf_counter() - t0
-        if n > 128:
-            t0 = time.perf_counter()
-            binv.invert_mixed(A, block=blk(n), out=X, ctx=ctx, lookahead=n >= 4096, from_fp64=True,
-                              sampled_check=True)
-            torch.cuda.synchronize()
-            t_checked += time.perf_counter() - t0
-        else:
-            t_checked += time.perf_counter() - t0
+        # the same sweep with the server's check at every order (the full
+        # residual below the probe estimate's minimum order)
+        t0 = time.perf_counter()
+        binv.invert_mixed(A, block=blk(n), out=X, ctx=ctx, lookahead=n >= 4096, from_fp64=True,
+                          sampled_check=True)
+        torch.cuda.synchronize()
+        t_checked += time.perf_counter() - t0
         if (i + 1) % 500 == 0:
             log(f"bench: serial {i + 1}/{N}: plain {t_plain:.1f} s, checked {t_checked:.1f} s")
     mu_plain = N / t_plain

@@ -81,10 +81,10 @@ typedef enum {
                              graph on first use and replay it afterwards.
                              Batched calls: one graph per plan, re-captured
                              when the A, X or info pointers change.
-                             binv_invert (with BINV_F_NO_LOOKAHEAD, required
-                             when there are two blocks or more: the two-stream
-                             lookahead schedule is not captured,
-                             BINV_E_INVALID otherwise): graphs cached in the
+                             binv_invert (one-stream schedule only: with two
+                             blocks or more, a call that would use the
+                             lookahead, see BINV_F_LOOKAHEAD, gives
+                             BINV_E_INVALID): graphs cached in the
                              context (at most 16, least recently used
                              replaced) keyed by n, the leading dimensions, the
                              A, X and info pointers, the flags and the
@@ -92,15 +92,21 @@ typedef enum {
                              (sizing the workspace), then captures; a key is
                              re-captured when the context's workspace has moved
                              since.  A replay reads A as it is at replay time. */
-#define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only.
-                             By default, block p+1's diagonal block is updated
-                             first, then block p+1's pivot block is inverted
-                             on an internal side stream while the rest of block
-                             p's trailing update runs on a second internal
-                             stream (CU-masked only if BINV_SIDE_NCU asks for
-                             it, see binv_lookahead_cus); the caller's stream
-                             waits for both before the call's work ends.
-                             Results are bitwise identical either way. */
+#define BINV_F_NO_LOOKAHEAD 2u /* run every step on the caller's stream only
+                             (the serial schedule). */
+#define BINV_F_LOOKAHEAD 64u /* use the lookahead schedule at every order:
+                             block p+1's diagonal block is updated first, then
+                             block p+1's pivot block is inverted on an internal
+                             side stream while the rest of block p's trailing
+                             update runs on a second internal stream
+                             (CU-masked only if BINV_SIDE_NCU asks for it, see
+                             binv_lookahead_cus); the caller's stream waits for
+                             both before the call's work ends.  With neither
+                             this flag nor BINV_F_NO_LOOKAHEAD the lookahead is
+                             used from n = 2048 up (below that the serial
+                             schedule measured as fast or faster); with both,
+                             BINV_F_NO_LOOKAHEAD wins.  Results are bitwise
+                             identical either way. */
 
 #define BINV_F_PIVOT 32u /* block-row pivoting (binv_invert, and the FP64 sweep of
                              binv_invert_mixed): the b_p rows that form pivot
@@ -199,7 +205,7 @@ binv_status binv_sweep_steps(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, c
  * (hipHostMalloc) makes the copies asynchronous; pageable memory works too.
  * Synchronous.  *singular_row (may be NULL): 0, or the 1-based row of the
  * first exactly-zero pivot (status BINV_E_SINGULAR; W is then undefined).
- * opts as for binv_invert (BINV_F_GRAPH and BINV_F_NO_LOOKAHEAD have no
+ * opts as for binv_invert (BINV_F_GRAPH, BINV_F_LOOKAHEAD and BINV_F_NO_LOOKAHEAD have no
  * effect); BINV_F_PIVOT and blocks of order > 2047 give BINV_E_INVALID.  The
  * host matrix is not checked for NaN or infinity. */
 binv_status binv_invert_host(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, const binv_opts* opts,
@@ -285,7 +291,7 @@ binv_status binv_residual_matrix(binv_ctx* ctx, int64_t n, const double* A, int6
 
 /* Invert A (FP64, row-major, lda) into X (ldx); X must not overlap A, which
  * is read again by the refinement.  opts: the partition (as binv_invert) and
- * the flags BINV_F_NO_LOOKAHEAD, BINV_F_REFINE_FROM_FP64, BINV_F_SAMPLED_CHECK.
+ * the flags BINV_F_LOOKAHEAD, BINV_F_NO_LOOKAHEAD, BINV_F_REFINE_FROM_FP64, BINV_F_SAMPLED_CHECK.
  * Refinement stops
  * once rho <= target (target <= 0 means 1e-10), after max_refine steps
  * (< 0 means 5, at most 6), or when rho stops decreasing.  Because the sweep

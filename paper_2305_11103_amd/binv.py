@@ -41,6 +41,7 @@ BINV_F_GRAPH = 4
 BINV_F_REFINE_FROM_FP64 = 8
 BINV_F_SAMPLED_CHECK = 16
 BINV_F_PIVOT = 32
+BINV_F_LOOKAHEAD = 64
 BINV_RESID_ESTIMATE = 1
 BINV_RESID_COMPENSATED = 2
 BINV_SERVER_STRICT_PRECISION = 1
@@ -241,7 +242,7 @@ def default_context(device: int = 0) -> Context:
     return _ctx[device]
 
 
-def _opts(part=None, block=None, sync=False, lookahead=True, pivot=False):
+def _opts(part=None, block=None, sync=False, lookahead=None, pivot=False):
     o = _Opts()
     keep = None
     if part is not None:
@@ -253,7 +254,9 @@ def _opts(part=None, block=None, sync=False, lookahead=True, pivot=False):
         o.k = 0
         o.part = None
     o.block = int(block) if block else 0
-    o.flags = (BINV_F_SYNC if sync else 0) | (0 if lookahead else BINV_F_NO_LOOKAHEAD) | (BINV_F_PIVOT if pivot else 0)
+    # lookahead: None lets the library choose by order, True / False force it
+    look = 0 if lookahead is None else (BINV_F_LOOKAHEAD if lookahead else BINV_F_NO_LOOKAHEAD)
+    o.flags = (BINV_F_SYNC if sync else 0) | look | (BINV_F_PIVOT if pivot else 0)
     return o, keep
 
 
@@ -261,7 +264,7 @@ def _stream_handle(torch, device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=True,
+def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=None, ctx=None, lookahead=None,
            pivot=False, graph=False, _noalloc=False):
     """Invert the square float64 CUDA tensor A by blockwise (Schur-complement)
     inversion over the diagonal blocks `part` (or uniform blocks of `block`).
@@ -270,7 +273,9 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     inplace: overwrite A with its inverse.
     sync:    wait for completion and raise SingularError on an exactly-zero pivot.
     lookahead: form the next block's pivot and panels on a side stream while
-             the current trailing update runs (bitwise identical results).
+             the current trailing update runs (True: BINV_F_LOOKAHEAD; False:
+             BINV_F_NO_LOOKAHEAD; None: the library's choice, on from n = 2048).
+             Results are bitwise identical either way.
     pivot:   block-row pivoting (BINV_F_PIVOT): each pivot block's rows are
              chosen among all rows not yet used as pivots.
     graph:   replay the call's launch sequence from a HIP graph cached in the
@@ -316,7 +321,7 @@ def invert(A, part=None, block=None, out=None, inplace=False, sync=True, info=No
     return X
 
 
-def sweep_steps(W, p_begin, p_end=-1, part=None, block=None, sync=True, info=None, ctx=None, lookahead=True):
+def sweep_steps(W, p_begin, p_end=-1, part=None, block=None, sync=True, info=None, ctx=None, lookahead=None):
     """Steps [p_begin, p_end) of the blockwise sweep in place on the float64
     CUDA tensor W (binv_sweep_steps); W holds A before step 0 and the state a
     previous range left otherwise.  Returns W."""
@@ -350,13 +355,15 @@ def invert_host(W, device_bytes, part=None, block=None, ctx=None, device=0):
     import torch
 
     if isinstance(W, torch.Tensor):
-        if W.is_cuda or W.dtype != torch.float64 or W.dim() != 2 or W.shape[0] != W.shape[1] or W.stride(1) != 1:
+        if (W.is_cuda or W.dtype != torch.float64 or W.dim() != 2 or W.shape[0] != W.shape[1]
+                or (W.numel() and W.stride(1) != 1)):
             raise ValueError("W must be a square row-major float64 host tensor")
         ptr, n, ld = W.data_ptr(), W.shape[0], W.stride(0)
     else:
-        if W.dtype != np.float64 or W.ndim != 2 or W.shape[0] != W.shape[1] or W.strides[1] != 8:
+        # (an empty array's strides carry no layout, so they are not checked)
+        if W.dtype != np.float64 or W.ndim != 2 or W.shape[0] != W.shape[1] or (W.size and W.strides[1] != 8):
             raise ValueError("W must be a square row-major float64 array")
-        ptr, n, ld = W.ctypes.data, W.shape[0], W.strides[0] // 8
+        ptr, n, ld = W.ctypes.data, W.shape[0], (W.strides[0] // 8 if W.size else 1)
     ctx = ctx or default_context(device)
     o, keep = _opts(part, block, False, True, False)
     row = ctypes.c_int64(0)
@@ -376,7 +383,7 @@ def invert_noalloc(A, part=None, block=None, out=None, inplace=False, sync=True,
                   lookahead=False, _noalloc=True)
 
 
-def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=True,
+def invert_mixed(A, part=None, block=None, out=None, target=1e-10, max_refine=5, ctx=None, lookahead=None,
                  from_fp64=False, sampled_check=False, pivot=False):
     """Mixed-precision inversion: FP32 blockwise sweep (FP64 pivot blocks), then
     FP64 Newton-Schulz refinement to rho = ||AX - I||_F / sqrt(n) <= target.

@@ -30,6 +30,18 @@ binv_status fail(binv_status st, const std::string& msg) {
   return st;
 }
 
+// Lookahead schedule of a call: BINV_F_NO_LOOKAHEAD forces it off,
+// BINV_F_LOOKAHEAD on; otherwise it is used from order kLookaheadMinN up.
+// Below that the serial schedule was measured as fast or faster (plain FP64,
+// every block size from 128 to 512: 0.86-1.0 of the serial time's speed at
+// n <= 1536, 0.98-1.06 at n = 2048, 1.01-1.16 from n = 3072).
+constexpr int64_t kLookaheadMinN = 2048;
+bool use_lookahead(uint32_t flags, int64_t n) {
+  if (flags & BINV_F_NO_LOOKAHEAD) return false;
+  if (flags & BINV_F_LOOKAHEAD) return true;
+  return n >= kLookaheadMinN;
+}
+
 }  // namespace
 
 void binv::set_error(const std::string& msg) { g_err = msg; }
@@ -908,7 +920,7 @@ binv_status invert_enqueue(binv_ctx* ctx, int64_t n, const double* A, int64_t ld
     if (e != hipSuccess) return fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e));
   }
   if (n == 0) return BINV_OK;
-  const bool look = !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2;
+  const bool look = use_lookahead(flags, n) && part.size() >= 2;
   // out of place with the lookahead: block 0's pivot inversion reads A and
   // runs on the side stream beside the copy of A into X
   const bool early = look && !inplace && !(flags & BINV_F_PIVOT);
@@ -924,7 +936,7 @@ binv_status invert_enqueue(binv_ctx* ctx, int64_t n, const double* A, int64_t ld
     hipError_t e = binv::launch_copy2d_check(A, lda, X, ldx, n, n, info, s);
     if (e != hipSuccess) return fail(BINV_E_HIP, std::string("copy: ") + hipGetErrorString(e));
   }
-  if (flags & BINV_F_PIVOT) return sweep_pivoted(ctx, n, X, ldx, part, s, info, !(flags & BINV_F_NO_LOOKAHEAD));
+  if (flags & BINV_F_PIVOT) return sweep_pivoted(ctx, n, X, ldx, part, s, info, use_lookahead(flags, n));
   return sweep(ctx, 0, n, X, ldx, part, s, info, 0, look, early ? A : nullptr, lda);
 }
 
@@ -1082,7 +1094,7 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
     if (e != hipSuccess) { st = fail(BINV_E_HIP, hipGetErrorString(e)); goto out; }
   }
   {
-    const bool look = !(opts && (opts->flags & BINV_F_NO_LOOKAHEAD));
+    const bool look = use_lookahead(opts ? opts->flags : 0u, n);
     const bool from64 = opts && (opts->flags & BINV_F_REFINE_FROM_FP64);
     const bool pivot = opts && (opts->flags & BINV_F_PIVOT);
     // small orders take the full residual, which is as cheap as the estimate there
@@ -1220,11 +1232,11 @@ binv_status binv_invert(binv_ctx* ctx, int64_t n, const double* A, int64_t lda, 
     if ((st = ctx->info.ensure(sizeof(long long))) != BINV_OK) goto out;
     info = (long long*)ctx->info.p;
   }
-  if ((flags & BINV_F_GRAPH) && !(flags & BINV_F_NO_LOOKAHEAD) && part.size() >= 2) {
+  if ((flags & BINV_F_GRAPH) && use_lookahead(flags, n) && part.size() >= 2) {
     // the first capture of the two-stream lookahead schedule ended the process
     // (a host-side crash during capture) and its cause is not known, so only
     // the one-stream schedule is captured
-    st = fail(BINV_E_INVALID, "BINV_F_GRAPH needs BINV_F_NO_LOOKAHEAD (the lookahead schedule is not captured)");
+    st = fail(BINV_E_INVALID, "BINV_F_GRAPH needs the one-stream schedule (BINV_F_NO_LOOKAHEAD, or n < 2048 without BINV_F_LOOKAHEAD)");
     goto out;
   }
   if (flags & BINV_F_GRAPH) {
@@ -1301,7 +1313,7 @@ binv_status binv_sweep_steps(binv_ctx* ctx, int64_t n, double* W, int64_t ldw, c
     if (e != hipSuccess) { st = fail(BINV_E_HIP, std::string("zero info: ") + hipGetErrorString(e)); goto out; }
   }
   if (n > 0 && p_end > p_begin) {
-    const bool look = !(flags & BINV_F_NO_LOOKAHEAD);
+    const bool look = use_lookahead(flags, n);
     if ((st = sweep(ctx, 0, n, W, ldw, part, s, info, 0, look, nullptr, 0, p_begin, p_end)) != BINV_OK) goto out;
   }
   if (flags & BINV_F_SYNC) {

@@ -1274,7 +1274,11 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
   __syncthreads();
 
   const int w = a.w;
-  double v[RPL][CPW];
+  // row half h of this wave's 16 columns (a vector, so that the next
+  // column's slot, a uniform index, is one indexed register move)
+  typedef double v16d __attribute__((ext_vector_type(16)));
+  static_assert(CPW == 16, "one 16-wide vector per row half");
+  v16d v[RPL];
   bool used[RPL];
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
@@ -1300,6 +1304,13 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
       s_pv[0] = pv;
     }
   }
+  // Per column c: the pivot row's values in this wave's columns (read from
+  // lane r % 64 of row half r / 64, a uniform choice), the multipliers, then
+  // column c + 1 by its owner wave and its pivot search, then every other
+  // slot.  Columns up to c are never read again, so their slots are updated
+  // too (the rows' values there no longer matter) and every register index is
+  // a constant; only the next column's slot (a uniform index) is chosen at run
+  // time.
   int got = 0, zero = -1;
   for (int c = 0; c < w; ++c) {
     const int buf = c & 1;
@@ -1316,11 +1327,10 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
     double sp[CPW];
 #pragma unroll
     for (int j = 0; j < CPW; ++j) {
-      double t = 0.0;
+      double t = v[0][j];
 #pragma unroll
-      for (int h = 0; h < RPL; ++h)
-        if (h == rh) t = readlane_f64(v[h][j], rl);
-      sp[j] = t;
+      for (int h = 1; h < RPL; ++h) t = (h == rh) ? v[h][j] : t;
+      sp[j] = readlane_f64(t, rl);
     }
     double f[RPL];
 #pragma unroll
@@ -1330,23 +1340,17 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
       f[h] = (used[h] || isr) ? 0.0 : colbuf[buf][i] * q;
       used[h] = used[h] || isr;
     }
-    // column c + 1 first, then its search, then the rest of the update
     const int cn = c + 1;
     const bool nowner = (cn < w) && (cn / CPW == wave);
-    const int jn = cn % CPW;
-#pragma unroll
-    for (int j = 0; j < CPW; ++j)
-      if (j == jn && nowner)
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
+    const int sn = cn % CPW;
     if (nowner) {
       double x[RPL];
 #pragma unroll
       for (int h = 0; h < RPL; ++h) {
-        x[h] = 0.0;
+        double pj = 0.0;
 #pragma unroll
-        for (int j = 0; j < CPW; ++j)
-          if (j == jn) x[h] = v[h][j];
+        for (int j = 0; j < CPW; ++j) pj = (j == sn) ? sp[j] : pj;
+        x[h] = fma(-f[h], pj, v[h][sn]);
       }
       double pv2;
       const int r2 = tourn_search<RPL>(x, used, pv2);
@@ -1358,12 +1362,9 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
       }
     }
 #pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const int col = wave * CPW + j;
-      if (col > c && !(j == jn && nowner))
+    for (int j = 0; j < CPW; ++j)
 #pragma unroll
-        for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
-    }
+      for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
   }
   __syncthreads();
   if (tid < 64) {

@@ -34,7 +34,9 @@
 
 namespace {
 
-constexpr int kSmallMax = 128;     // orders batched into shared launches
+constexpr int kSmallMax = 128;     // orders inverted by the register tiers of a round
+constexpr int kRoundMax = 256;     // orders grouped into rounds (above kSmallMax: swept steps)
+constexpr int kSweptBlock = 128;   // largest diagonal block of a swept step
 constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 3)
 constexpr int kMaxRoundSmall = 65536;
 constexpr int64_t kBigN = 4096;    // orders served one at a time on worker 0
@@ -90,16 +92,26 @@ size_t block_bytes(int64_t n) { return size_class(2 * sizeof(double) * std::max<
 // Diagonal-block order the workers use for a request of order n.
 int worker_block(int64_t n) { return n >= 2048 ? 512 : (n >= 512 ? 256 : 128); }
 
+// Does a request run in a round (shared launches) rather than on a worker?
+// Orders up to kSmallMax always do; kSmallMax < n <= kRoundMax unless the
+// request starts from the FP32 sweep, which only the workers run.
+bool in_round(int64_t n, bool fp32_start) { return n <= kSmallMax || (n <= kRoundMax && !fp32_start); }
+
 // Upper bound of the workspace a request makes the server hold while it runs:
-// for orders <= kSmallMax its share of a round's buffers (packed copies of A
-// and X, two m x m refinement buffers, the tables); above that what a worker
+// in a round its share of the round's buffers (packed copies of A and X, two
+// m x m refinement buffers, the tables, and for a swept order the pivot
+// inverse and the two panels of its steps); otherwise what a worker
 // context's binv_invert_mixed can grow to for it: the sweep's panels (two
 // sets under the lookahead) and the nested pivot sweep's, the residual and
 // next iterate, the compensated residual's split operands, and the FP32
 // working copy and panels when it starts from the FP32 sweep.
 size_t workspace_bytes(int64_t n, bool fp32_start) {
   const size_t nn = (size_t)n * (size_t)n, d = sizeof(double);
-  if (n <= kSmallMax) return 4 * d * nn + 64;
+  if (in_round(n, fp32_start)) {
+    size_t w = 4 * d * nn + 64;
+    if (n > kSmallMax) w += d * (kSweptBlock * kSweptBlock + 2 * kSweptBlock * (size_t)n) + 4 * sizeof(binv::SweptJob);
+    return w;
+  }
   const size_t b = (size_t)worker_block(n), sets = n >= kBigN ? 2 : 1;
   size_t w = sets * d * (2 * b * (size_t)n + b * b);  // level-0 panels and pivot inverse
   w += 2 * d * (2 * 64 * b + 64 * 64);               // the nested pivot sweep's panels
@@ -120,7 +132,7 @@ struct binv_server {
   std::condition_variable wcv;     // wakes the workers
   std::deque<Request*> queue;      // submitted, not admitted
   std::deque<Request*> big_ready;   // order >= kBigN: worker 0 only, one at a time
-  std::deque<Request*> mid_ready;   // kSmallMax < order < kBigN: any worker
+  std::deque<Request*> mid_ready;   // other orders below kBigN: any worker
   std::vector<Request*> small_ready;
   std::unordered_map<uint64_t, Request*> all;
   std::deque<uint64_t> done_q;     // finished tickets in completion order
@@ -145,7 +157,7 @@ struct binv_server {
   // copies in and out of request state; every copy is waited for, so a
   // worker stream never reads a block before its input has landed
   hipStream_t cstream = nullptr;
-  binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo, rwork, rtarget, rrho, rsteps;
+  binv::DevBuf rA, rX, rmats, rorder, rbounds, rinfo, rwork, rtarget, rrho, rsteps, rsw, rjobs;
   // Accounting: `used` counts every byte the server holds on the device or
   // has promised: blocks of admitted requests, blocks kept in the cache,
   // workspace held by the worker contexts (ws_held) and by the round buffers
@@ -258,7 +270,7 @@ bool make_room_locked(binv_server* s, Request* r, bool scheduler) {
   if (s->used + need > s->budget) (void)trim_workers_locked(s, need);
   if (s->used + need > s->budget && scheduler && s->round_held > 0) {
     for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork, &s->rtarget,
-                            &s->rrho, &s->rsteps})
+                            &s->rrho, &s->rsteps, &s->rsw, &s->rjobs})
       d->release();
     s->used -= s->round_held;
     s->round_held = 0;
@@ -310,13 +322,19 @@ void request_release_locked(binv_server* s, Request* r) {
   r->dA = r->dX = nullptr;
 }
 
+// Does the request start from the FP32 sweep (a mixed request whose target
+// is within that sweep's reach, or any mixed request under strict precision)?
+bool fp32_start_of(const binv_server* s, const Request* r) {
+  return r->prec == BINV_PREC_MIXED_F32 && ((s->flags & BINV_SERVER_STRICT_PRECISION) || r->target >= kFp32Reach);
+}
+
 // Queue an admitted request for its lane (mu held).  Large orders run one at
 // a time on worker 0, with the lookahead schedule: one sweep of that size
 // already keeps the device busy, and two of them side by side were measured
 // slower than one after the other.  Mid orders are latency-bound sweeps that
 // the other workers overlap with it and with each other.
 void route_locked(binv_server* s, Request* r) {
-  if (r->n <= kSmallMax) {
+  if (in_round(r->n, fp32_start_of(s, r))) {
     s->small_ready.push_back(r);
     return;
   }
@@ -354,13 +372,30 @@ void admit_locked(binv_server* s) {
   }
 }
 
-// One scheduling round of the small path: pack, invert, unpack.
+// Block orders of a swept request: m split into ceil(m / kSweptBlock) near-equal
+// blocks, the larger ones last.
+std::vector<int> swept_blocks(int m) {
+  const int pieces = (m + kSweptBlock - 1) / kSweptBlock;
+  std::vector<int> ord(pieces);
+  for (int q = 0; q < pieces; ++q) ord[q] = m / pieces + (q >= pieces - m % pieces ? 1 : 0);
+  return ord;
+}
+
+// One scheduling round: pack, invert, check and refine, unpack.  Orders up to
+// kSmallMax are inverted by the register tiers (one diagonal block, pivoting
+// over the whole matrix).  Larger orders are swept block by block (Eq. (a)
+// unrolled): the requests' matrices are the round's device-resident state, and
+// block step p of every request that has one runs in one shared launch
+// (k_swept_step, one workgroup per request: pivot leaf, row panel, column-panel
+// copy, Schur update), so each step index is one launch for the whole round.
 void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
   const int64_t cnt = (int64_t)reqs.size();
   std::vector<binv::SmallMat> mats(cnt);
   std::vector<int32_t> bounds;
   std::vector<std::vector<int32_t>> tiers(5);
-  int64_t off = 0;
+  std::vector<int32_t> swept;  // request indices of the swept orders
+  std::vector<int64_t> sw_off;  // their workspace offsets (elements)
+  int64_t off = 0, sw_elems = 0;
   for (int64_t i = 0; i < cnt; ++i) {
     const int m = (int)reqs[i]->n;
     mats[i].off = off;
@@ -370,9 +405,15 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
     mats[i].id = (int32_t)i;
     bounds.push_back(0);
     bounds.push_back(m);
-    int t = 0;
-    while (m > binv::small_tier_limit(t)) ++t;
-    tiers[t].push_back((int32_t)i);
+    if (m > kSmallMax) {
+      swept.push_back((int32_t)i);
+      sw_off.push_back(sw_elems);
+      sw_elems += (int64_t)kSweptBlock * kSweptBlock + 2LL * kSweptBlock * m;
+    } else {
+      int t = 0;
+      while (m > binv::small_tier_limit(t)) ++t;
+      tiers[t].push_back((int32_t)i);
+    }
     off += (int64_t)m * m;
   }
   std::vector<int32_t> order;
@@ -394,8 +435,61 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
       (e = s->rwork.ensure(sizeof(double) * 2 * std::max<int64_t>(off, 1))) != BINV_OK ||
       (e = s->rtarget.ensure(sizeof(double) * cnt)) != BINV_OK ||
       (e = s->rrho.ensure(sizeof(double) * cnt)) != BINV_OK ||
-      (e = s->rsteps.ensure(sizeof(int32_t) * cnt)) != BINV_OK) {
+      (e = s->rsteps.ensure(sizeof(int32_t) * cnt)) != BINV_OK ||
+      (e = s->rsw.ensure(sizeof(double) * std::max<int64_t>(sw_elems, 1))) != BINV_OK) {
     err = "round buffers: out of device memory";
+  }
+  // the swept steps' jobs: step p of request i reads its matrix as left by
+  // step p - 1 (A itself for p = 0) and writes X; P, Ct and R live in the
+  // request's slice of the round workspace
+  std::vector<binv::SweptJob> jobs;
+  std::vector<std::pair<int64_t, int64_t>> step_jobs;  // (first job, jobs with a block > 64) per step
+  std::vector<int64_t> step_count;
+  if (e == BINV_OK && !swept.empty()) {
+    const double* A = (const double*)s->rA.p;
+    double* X = (double*)s->rX.p;
+    double* ws = (double*)s->rsw.p;
+    std::vector<std::vector<int>> blocks;
+    size_t steps = 0;
+    for (int32_t i : swept) {
+      blocks.push_back(swept_blocks(mats[i].m));
+      steps = std::max(steps, blocks.back().size());
+    }
+    for (size_t p = 0; p < steps; ++p) {
+      const int64_t first = (int64_t)jobs.size();
+      for (size_t t = 0; t < swept.size(); ++t) {
+        const int i = swept[t];
+        if (p >= blocks[t].size()) continue;
+        const int m = mats[i].m;
+        int o = 0;
+        for (size_t q = 0; q < p; ++q) o += blocks[t][q];
+        const int bs = blocks[t][p];
+        const double* Win = (p == 0 ? A : (const double*)X) + mats[i].off;
+        double* Wout = X + mats[i].off;
+        double* P = ws + sw_off[t];
+        double* Ct = P + kSweptBlock * kSweptBlock;
+        double* R = Ct + (int64_t)kSweptBlock * m;
+        binv::SweptJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.leaf.A = Win + (int64_t)o * m + o; j.leaf.lda = m; j.leaf.P = P; j.leaf.ldp = bs; j.leaf.b = bs;
+        j.leaf.row0 = o; j.leaf.info = (int32_t*)s->rinfo.p + i;
+        binv::StepArgs& ra = j.row;
+        ra.A = P; ra.lda = bs; ra.B = Win + (int64_t)o * m; ra.ldb = m; ra.W = R; ra.ldw = m;
+        ra.R = P; ra.ldr = bs; ra.M = bs; ra.N = m; ra.K = bs; ra.o = o; ra.b = bs; ra.oc = o;
+        binv::StepArgs& sa = j.schur;
+        sa.A = Ct; sa.lda = bs; sa.B = R; sa.ldb = m; sa.W = Wout; sa.ldw = m; sa.Win = Win; sa.ldwin = m;
+        sa.R = R; sa.ldr = m; sa.M = m; sa.N = m; sa.K = bs; sa.o = o; sa.b = bs; sa.oc = o;
+        jobs.push_back(j);
+      }
+      std::stable_sort(jobs.begin() + first, jobs.end(),
+                       [](const binv::SweptJob& x, const binv::SweptJob& y) { return x.leaf.b > y.leaf.b; });
+      int64_t big = 0;
+      for (int64_t q = first; q < (int64_t)jobs.size(); ++q) big += jobs[q].leaf.b > 64;
+      step_jobs.emplace_back(first, big);
+      step_count.push_back((int64_t)jobs.size() - first);
+    }
+    if ((e = s->rjobs.ensure(sizeof(binv::SweptJob) * jobs.size())) != BINV_OK)
+      err = "round buffers: out of device memory";
   }
   std::vector<int32_t> hinfo(cnt, 0), hsteps(cnt, 0);
   std::vector<double> htarget(cnt), hrho(cnt, 0.0);
@@ -408,12 +502,25 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
       he = hipMemcpyAsync(A + mats[i].off, reqs[i]->dA, sizeof(double) * mats[i].m * mats[i].m,
                           hipMemcpyDeviceToDevice, st);
     if (he == hipSuccess) he = hipMemcpyAsync(s->rmats.p, mats.data(), sizeof(binv::SmallMat) * cnt, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipMemcpyAsync(s->rorder.p, order.data(), sizeof(int32_t) * cnt, hipMemcpyHostToDevice, st);
+    // (the register tiers' members only: the swept orders are not in it)
+    if (he == hipSuccess && !order.empty())
+      he = hipMemcpyAsync(s->rorder.p, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice, st);
     if (he == hipSuccess)
       he = hipMemcpyAsync(s->rbounds.p, bounds.data(), sizeof(int32_t) * bounds.size(), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess && !jobs.empty()) {
+      he = hipMemcpyAsync(s->rjobs.p, jobs.data(), sizeof(binv::SweptJob) * jobs.size(), hipMemcpyHostToDevice, st);
+      // the leaves record a zero pivot with a compare-and-swap on a zeroed word
+      if (he == hipSuccess) he = hipMemsetAsync(s->rinfo.p, 0, sizeof(int32_t) * cnt, st);
+    }
     for (int t = 0; t < 5 && he == hipSuccess; ++t)
       he = binv::launch_small_tier(t, A, X, (const binv::SmallMat*)s->rmats.p, (const int32_t*)s->rorder.p + first[t],
                                    count[t], (const int32_t*)s->rbounds.p, (int32_t*)s->rinfo.p, st);
+    for (size_t p = 0; p < step_jobs.size() && he == hipSuccess; ++p) {
+      const binv::SweptJob* dj = (const binv::SweptJob*)s->rjobs.p + step_jobs[p].first;
+      he = binv::launch_swept_step(dj, step_jobs[p].second, 128, st);
+      if (he == hipSuccess)
+        he = binv::launch_swept_step(dj + step_jobs[p].second, step_count[p] - step_jobs[p].second, 64, st);
+    }
     // residual check of every matrix against its request's target, with up to
     // three Newton-Schulz steps where it misses (a singular member's X is not
     // used, so its refinement result does not matter)
@@ -441,7 +548,7 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
     // reservations end with the round
     size_t held = 0;
     for (const binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork,
-                                  &s->rtarget, &s->rrho, &s->rsteps})
+                                  &s->rtarget, &s->rrho, &s->rsteps, &s->rsw, &s->rjobs})
       held += d->bytes;
     std::lock_guard<std::mutex> g(s->mu);
     s->used += held;
@@ -754,7 +861,7 @@ binv_status binv_server_destroy(binv_server* s) {
   for (auto& kv : s->pool) (void)hipFree(kv.second);
   for (int w = 0; w < s->nworkers; ++w) binv_destroy(s->wctx[w]);
   for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork, &s->rtarget,
-                          &s->rrho, &s->rsteps})
+                          &s->rrho, &s->rsteps, &s->rsw, &s->rjobs})
     d->release();
   if (s->rstream) (void)hipStreamDestroy(s->rstream);
   if (s->cstream) (void)hipStreamDestroy(s->cstream);

@@ -181,8 +181,10 @@ def test_invalid_partition_rejected(gpu):
 @pytest.mark.parametrize("n,part", [(1000, [200, 300, 500]), (1536, [512, 512, 512]), (700, None), (2304, None)])
 def test_lookahead_is_bitwise_identical(gpu, n, part):
     A = wl.diag_dominant(n, 77 + n)
-    X1 = _inv(A, part=part, block=None if part else 256)
+    X1 = _inv(A, part=part, block=None if part else 256, lookahead=True)
     X2 = _inv(A, part=part, block=None if part else 256, lookahead=False)
+    X3 = _inv(A, part=part, block=None if part else 256)  # the library's choice by order
+    assert np.array_equal(X1, X3)
     assert np.array_equal(X1, X2)
     _check(A, X1)
 
@@ -311,13 +313,14 @@ def test_non_finite_with_a_zero_pivot_reports_invalid(gpu):
 
 _LOOKAHEAD_CAPTURE_OFF = ("capture of the two-stream lookahead schedule ended the test process with a host "
                           "segmentation fault on its first run (no GPU fault); the cause is not found, so that "
-                          "path is switched off (BINV_F_GRAPH needs BINV_F_NO_LOOKAHEAD)")
+                          "path is switched off (BINV_F_GRAPH needs the one-stream schedule)")
 
 
 @pytest.mark.parametrize("n,part,look", [
     pytest.param(256, [64] * 4, True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF)),
     pytest.param(1536, [512, 512, 512], True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF)),
     (700, [300, 400], False), (256, [64] * 4, False), (1536, [512, 512, 512], False),
+    (256, [64] * 4, None), (1000, [200, 300, 500], None),  # below n = 2048 the default is the serial schedule
     pytest.param(1000, [200, 300, 500], True, marks=pytest.mark.skip(reason=_LOOKAHEAD_CAPTURE_OFF))])
 def test_graph_replays_match_eager_every_time(gpu, n, part, look):
     """BINV_F_GRAPH: the first call runs eagerly and captures; every later
@@ -355,10 +358,16 @@ def test_graph_singular_and_non_finite_through_replays(gpu):
     A_np = wl.diag_dominant(n, 33)
     A = torch.from_numpy(A_np).cuda()
     X = torch.empty_like(A)
-    # graph capture needs the one-stream schedule (rejected before any launch)
+    # graph capture needs the one-stream schedule (rejected before any launch):
+    # the lookahead asked for, or the library's default from n = 2048
     with pytest.raises(binv.BinvError) as e:
-        binv.invert(A, part=part, out=X, graph=True)
+        binv.invert(A, part=part, out=X, graph=True, lookahead=True)
     assert e.value.status == binv.BINV_E_INVALID
+    big = torch.eye(2048, dtype=torch.float64, device="cuda")
+    with pytest.raises(binv.BinvError) as e:
+        binv.invert(big, block=512, graph=True)
+    assert e.value.status == binv.BINV_E_INVALID
+    del big
     kw = dict(part=part, out=X, graph=True, lookahead=False)
     binv.invert(A, **kw)
     binv.invert(A, **kw)

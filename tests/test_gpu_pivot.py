@@ -117,7 +117,7 @@ def test_pivoted_lookahead_inplace_bitwise(gpu):
     A_np = wl.general_haar(n, wl.stream_seed(3, 400), 1e4)
     part = [512, 384, 640]
     A = torch.from_numpy(A_np).cuda()
-    X1 = binv.invert(A, part=part, pivot=True)
+    X1 = binv.invert(A, part=part, pivot=True, lookahead=True)
     X2 = binv.invert(A, part=part, pivot=True, lookahead=False)
     X3 = A.clone()
     binv.invert(X3, part=part, pivot=True, inplace=True)
