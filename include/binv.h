@@ -316,10 +316,12 @@ binv_status binv_invert_mixed(binv_ctx* ctx, int64_t n, const double* A, int64_t
  * running sum of k (part == NULL: floor(m/k) each, the remainder added one by
  * one to the last blocks).  Each matrix is inverted by the same blockwise
  * elimination as binv_invert, with pivoting inside its diagonal blocks only;
- * blocks larger than 128 of a matrix of order > 128 are split in near-equal
- * pieces of at most 128.  Host arrays are read during binv_batch_create only.
- * The plan keeps device copies of its tables and a workspace of about
- * (128^2 + 256 m) doubles per matrix of order > 128; it belongs to `ctx`'s
+ * orders up to 192 run in registers, one Gauss-Jordan pass per matrix; blocks
+ * larger than 128 of a matrix of order > 192 are split in near-equal pieces
+ * of at most 128, and such a matrix is swept block step by block step.  Host
+ * arrays are read during binv_batch_create only.  The plan keeps device
+ * copies of its tables and a workspace of about (128^2 + 256 m) doubles per
+ * matrix of order > 192; it belongs to `ctx`'s
  * device and is released by binv_batch_destroy.
  * Errors: BINV_E_INVALID for an order outside 1..256, k[i] outside 1..m[i] or
  * block orders that do not sum to m[i]; BINV_E_NOMEM.
@@ -372,7 +374,7 @@ binv_status binv_invert_batched_levels(binv_batch* plan, const double* A, double
  * capacity below N_k. */
 binv_status binv_level_partition(int32_t m, int32_t capacity, int32_t* k, int32_t* part);
 
-/* Autotuner for the register-resident tiers (orders <= 128).  Each tier has
+/* Autotuner for the register-resident tiers (orders <= 192).  Each tier has
  * several launch shapes (rows per lane, columns per wave, waves per matrix,
  * matrices per workgroup) that compute bitwise-identical results; this call
  * runs every shape of every non-empty tier `reps` times (>= 1) on the plan's
@@ -381,10 +383,11 @@ binv_status binv_level_partition(int32_t m, int32_t capacity, int32_t* k, int32_
  * keeps the fastest in the plan.  The choice is also remembered in `ctx` by
  * tier and by the power of two of the tier's matrix count, and plans created
  * later on that context start from it.  Synchronous.  chosen (may be NULL):
- * int32[5], the shape index per tier (-1 for an empty tier); ms (may be
- * NULL): double[5 * 4], the best time of each (tier, shape), 0 when not run
- * (tiers have 4, 4, 4, 4 and 3 shapes; the last tier's third shape is its
- * first compiled for two workgroups per CU). */
+ * int32[6], the shape index per tier (-1 for an empty tier); ms (may be
+ * NULL): double[6 * 4], the best time of each (tier, shape), 0 when not run
+ * (tiers up to orders 8, 16, 32, 64, 128, 192 have 4, 4, 4, 4, 3 and 2
+ * shapes; the fifth tier's third shape is its first compiled for two
+ * workgroups per CU). */
 binv_status binv_batch_tune(binv_batch* plan, const double* A, double* X, int32_t* d_info, int32_t reps,
                             void* stream, int32_t* chosen, double* ms);
 
@@ -411,22 +414,24 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * staged in host memory until admission.  A scheduler thread admits queued requests in FIFO
  * order while the server's HBM budget (bytes of device memory held for
  * admitted, not yet collected requests, including their working panels) and
- * in-flight limit allow.  Admitted requests of order <= 128 are grouped into
- * shared batched launches (one Gauss-Jordan pass each, pivoting over the
- * whole matrix); larger ones are inverted by the blockwise sweep on worker
- * threads with their own streams, so their work overlaps on the device:
- * orders >= 4096 one at a time on the first worker (with the lookahead
- * schedule), orders 129..4095 on any worker (BINV_SERVER_WORKERS in the
- * environment sets the worker count, default 3).
- * Every request of order > 128 ends with the FP64 residual check against its
+ * in-flight limit allow.  Admitted requests of order <= 256 are grouped into
+ * rounds of shared batched launches: orders <= 192 one Gauss-Jordan pass each
+ * in registers (pivoting over the whole matrix), orders 193..256 swept block
+ * step by block step with blocks of at most 128 (one launch per step for
+ * every such request of the round); a mixed request that starts from the FP32
+ * sweep (see BINV_SERVER_STRICT_PRECISION) and every larger request is
+ * inverted by the blockwise sweep on worker threads with their own streams,
+ * so their work overlaps on the device: orders >= 4096 one at a time on the
+ * first worker (with the lookahead schedule), the others on any worker
+ * (BINV_SERVER_WORKERS in the environment sets the worker count, default 3).
+ * Every request run by a worker ends with the FP64 residual check against its
  * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check
  * fails; the check asks for half the target (it carries rounding error and,
  * as an estimate, a spread of its own), info->converged reports rho <= target.
  * BINV_PREC_FP64 starts from the FP64 sweep; BINV_PREC_MIXED_F32 from
  * the FP32 sweep under the policy of BINV_SERVER_STRICT_PRECISION below.
- * Requests of order <= 128 are inverted in FP64 (Gauss-Jordan with pivoting
- * over the whole matrix, shared launches), then checked on their full
+ * Requests run in a round are inverted in FP64, then checked on their full
  * residual and refined by up to three Newton-Schulz steps where they miss
  * their target (info->sampled = 0).
  * binv_poll returns BINV_E_BUSY until the request is done; then it copies X
@@ -490,7 +495,7 @@ binv_status binv_server_destroy(binv_server* server);
 #define BINV_PHASE_OTHER 3   /* copies and panel saves */
 #define BINV_PHASE_BAND 4    /* lookahead: Schur update of the next block's
                                 diagonal block, before the fork */
-#define BINV_PHASE_SMALL 5   /* batched: register-resident tiers (orders <= 128) */
+#define BINV_PHASE_SMALL 5   /* batched: register-resident tiers (orders <= 192) */
 #define BINV_PHASE_TAIL 6    /* lookahead: the part of the trailing update that
                                 follows the pivot chain on the side stream */
 #define BINV_NPHASE 7

@@ -47,7 +47,8 @@ BINV_RESID_COMPENSATED = 2
 BINV_SERVER_STRICT_PRECISION = 1
 BINV_SERVER_FULL_CHECK = 2
 PHASES = ("pivot", "row", "schur", "other", "band", "small", "tail")
-TIER_SHAPES = (4, 4, 4, 4, 3)  # launch shapes per register tier (autotuned)
+TIER_SHAPES = (4, 4, 4, 4, 3, 2)  # launch shapes per register tier (autotuned)
+TIER_LIMITS = (8, 16, 32, 64, 128, 192)  # largest order of each register tier
 
 
 class BinvError(RuntimeError):
@@ -557,14 +558,15 @@ class Batch:
             raise ValueError("tuning needs a separate output buffer")
         if info is None:
             info = torch.empty(max(self.count, 1), dtype=torch.int32, device=A.device)
-        chosen = (ctypes.c_int32 * 5)()
-        ms = (ctypes.c_double * 20)()
+        chosen = (ctypes.c_int32 * len(TIER_SHAPES))()
+        ms = (ctypes.c_double * (4 * len(TIER_SHAPES)))()
         with torch.cuda.device(A.device):
             _check(load_library().binv_batch_tune(self._h, ctypes.c_void_p(A.data_ptr()),
                                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(info.data_ptr()),
                                                   int(reps), _stream_handle(torch, A.device.index or 0), chosen, ms))
-        return list(chosen), [list(ms[4 * t:4 * t + TIER_SHAPES[t]]) for t in range(5)], [
-            [batch_shape(t, v) for v in range(TIER_SHAPES[t])] for t in range(5)]
+        nt = len(TIER_SHAPES)
+        return list(chosen), [list(ms[4 * t:4 * t + TIER_SHAPES[t]]) for t in range(nt)], [
+            [batch_shape(t, v) for v in range(TIER_SHAPES[t])] for t in range(nt)]
 
     def residual(self, A, X):
         """rho_i = ||A_i X_i - I||_F / sqrt(m_i) for every matrix (float64 CUDA tensor)."""

@@ -160,9 +160,13 @@ k_small_inverse(const double* __restrict__ A, double* __restrict__ X, const Smal
       const int rl = __builtin_amdgcn_readfirstlane(r & 63);
       const int rh = (RPL == 1) ? 0 : __builtin_amdgcn_readfirstlane(r >> 6);
       double sp[CPW];
+      static_assert(RPL <= 3, "the pivot row's half is chosen among at most three");
       if (RPL == 1 || rh == 0) {
 #pragma unroll
         for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[0][j], rl) * q;
+      } else if (RPL == 3 && rh == 1) {
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[1 % RPL][j], rl) * q;
       } else {
 #pragma unroll
         for (int j = 0; j < CPW; ++j) sp[j] = bread_f64(v[RPL - 1][j], rl) * q;
@@ -356,14 +360,16 @@ hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats,
 struct TierShape {
   int rpl, cpw, nwv, sub;
 };
-static const TierShape kShapes[5][kSmallVariants] = {
+static const TierShape kShapes[kSmallTierCount][kSmallVariants] = {
     {{1, 8, 1, 4}, {1, 8, 1, 8}, {1, 8, 1, 2}, {1, 8, 1, 16}},      // m <= 8
     {{1, 16, 1, 4}, {1, 16, 1, 8}, {1, 8, 2, 4}, {1, 8, 2, 2}},     // m <= 16
     {{1, 32, 1, 4}, {1, 16, 2, 2}, {1, 8, 4, 1}, {1, 32, 1, 8}},    // m <= 32
     {{1, 16, 4, 1}, {1, 32, 2, 2}, {1, 8, 8, 1}, {1, 16, 4, 2}},    // m <= 64
-    {{2, 16, 8, 1}, {2, 8, 16, 1}, {2, 16, 8, 1}, {0, 0, 0, 0}},    // m <= 128 (wider shapes spill);
-};                                                                  // shape 2 = shape 0 at two workgroups per CU
-static const int kShapeCount[5] = {4, 4, 4, 4, 3};
+    {{2, 16, 8, 1}, {2, 8, 16, 1}, {2, 16, 8, 1}, {0, 0, 0, 0}},    // m <= 128 (wider shapes spill;
+                                                                    // shape 2 = shape 0 at two workgroups per CU)
+    {{3, 16, 12, 1}, {3, 24, 8, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},    // m <= 192 (one workgroup per CU)
+};
+static const int kShapeCount[kSmallTierCount] = {4, 4, 4, 4, 3, 2};
 
 template <int RPL, int CPW, int NWV, int SUB, int MINW = 1>
 hipError_t launch_shape(const double* A, double* X, const SmallMat* mats, const int32_t* order, int64_t count,
@@ -378,7 +384,7 @@ hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, 
                              const int32_t* order, int64_t count, const int32_t* bounds, int32_t* info,
                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (tier < 0 || tier >= 5 || variant < 0 || variant >= kShapeCount[tier]) return hipErrorInvalidValue;
+  if (tier < 0 || tier >= kSmallTierCount || variant < 0 || variant >= kShapeCount[tier]) return hipErrorInvalidValue;
 #define BINV_SHAPE(T, V, R, C, N, S) \
   if (tier == T && variant == V) return launch_shape<R, C, N, S>(A, X, mats, order, count, bounds, info, s);
   BINV_SHAPE(0, 0, 1, 8, 1, 4) BINV_SHAPE(0, 1, 1, 8, 1, 8) BINV_SHAPE(0, 2, 1, 8, 1, 2) BINV_SHAPE(0, 3, 1, 8, 1, 16)
@@ -387,6 +393,8 @@ hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, 
   BINV_SHAPE(3, 0, 1, 16, 4, 1) BINV_SHAPE(3, 1, 1, 32, 2, 2) BINV_SHAPE(3, 2, 1, 8, 8, 1) BINV_SHAPE(3, 3, 1, 16, 4, 2)
   BINV_SHAPE(4, 0, 2, 16, 8, 1) BINV_SHAPE(4, 1, 2, 8, 16, 1)
   if (tier == 4 && variant == 2) return launch_shape<2, 16, 8, 1, 4>(A, X, mats, order, count, bounds, info, s);
+  if (tier == 5 && variant == 0) return launch_shape<3, 16, 12, 1>(A, X, mats, order, count, bounds, info, s);
+  if (tier == 5 && variant == 1) return launch_shape<3, 24, 8, 1>(A, X, mats, order, count, bounds, info, s);
 #undef BINV_SHAPE
   return hipErrorInvalidValue;
 }
@@ -396,7 +404,7 @@ hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMa
   return launch_small_tier(tier, 0, A, X, mats, order, count, bounds, info, s);
 }
 
-int small_variant_count(int tier) { return (tier >= 0 && tier < 5) ? kShapeCount[tier] : 0; }
+int small_variant_count(int tier) { return (tier >= 0 && tier < kSmallTierCount) ? kShapeCount[tier] : 0; }
 
 void small_variant_shape(int tier, int variant, int shape[4]) {
   const TierShape& t = kShapes[tier][variant];
@@ -408,8 +416,8 @@ void small_variant_shape(int tier, int variant, int shape[4]) {
 
 // Largest order handled by each small tier.
 int small_tier_limit(int tier) {
-  static const int lim[5] = {8, 16, 32, 64, 128};
-  return (tier >= 0 && tier < 5) ? lim[tier] : 0;
+  static const int lim[kSmallTierCount] = {8, 16, 32, 64, 128, 192};
+  return (tier >= 0 && tier < kSmallTierCount) ? lim[tier] : 0;
 }
 
 }  // namespace binv

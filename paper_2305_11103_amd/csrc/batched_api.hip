@@ -1,9 +1,9 @@
 // C ABI of the batched inversion (binv_batch_*; declared in include/binv.h).
 //
 // A plan fixes the orders and diagonal-block partitions of a batch of small
-// matrices packed back to back.  Matrices of order <= 128 go to one of five
+// matrices packed back to back.  Matrices of order <= 192 go to one of six
 // register-resident tiers (k_small_inverse: one pass, pivoting restricted to
-// each diagonal block); orders 129..256 are swept block by block, one launch
+// each diagonal block); orders 193..256 are swept block by block, one launch
 // per step and shape class with one workgroup per matrix doing the whole step
 // (k_swept_step: pivot leaf, row panel, column-panel copy, Schur update), the
 // same Eq. (a) step as the single-matrix path.  All
@@ -21,7 +21,7 @@
 
 namespace {
 
-constexpr int kSmallTiers = 5;
+constexpr int kSmallTiers = binv::kSmallTierCount;
 constexpr int kBlockMax = 128;  // largest diagonal block of the swept tier
 
 binv_status bfail(binv_status st, const std::string& msg) {
@@ -75,7 +75,7 @@ struct binv_batch {
   void* d_mats = nullptr;    // SmallMat per matrix (all matrices)
   void* d_order = nullptr;   // matrix indices grouped by tier
   void* d_bounds = nullptr;  // diagonal-block boundaries
-  // swept tier (orders 129..256)
+  // swept tier (orders 193..256)
   std::vector<SweptStep> steps;
   std::vector<int32_t> swept;     // matrix indices
   std::vector<int64_t> ws_off;    // workspace offset (elements) per swept matrix
@@ -251,7 +251,7 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
     // the swept tier needs blocks of at most 128: split larger ones in halves
     std::vector<int> fin;
     for (int x : ord) {
-      if (mi > 128 && x > kBlockMax) {
+      if (mi > binv::kSmallMaxOrder && x > kBlockMax) {
         const int pieces = (x + kBlockMax - 1) / kBlockMax;
         for (int q = 0; q < pieces; ++q) fin.push_back(x / pieces + (q >= pieces - x % pieces ? 1 : 0));
       } else {
@@ -269,7 +269,7 @@ binv_status binv_batch_create(binv_ctx* ctx, int64_t count, const int32_t* m, co
     mats[i].nb = (int)fin.size();
     mats[i].bnd = b->bnd_index[i];
     mats[i].id = (int)i;
-    if (mi <= 128) {
+    if (mi <= binv::kSmallMaxOrder) {
       int t = 0;
       while (mi > binv::small_tier_limit(t)) ++t;
       tiers[t].push_back((int32_t)i);

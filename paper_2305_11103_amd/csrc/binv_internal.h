@@ -188,6 +188,8 @@ hipError_t launch_sum_final(const double* part, int np, double* out, hipStream_t
 
 // batched.hip
 constexpr int kSmallVariants = 4;  // most launch shapes of a small tier (autotuned)
+constexpr int kSmallTierCount = 6;  // register-resident tiers: orders up to 8, 16, 32, 64, 128, 192
+constexpr int kSmallMaxOrder = 192; // largest order of the register-resident tiers
 hipError_t launch_small_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                              int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s);
 hipError_t launch_small_tier(int tier, int variant, const double* A, double* X, const SmallMat* mats,
@@ -304,7 +306,7 @@ struct binv_ctx {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_gemm = nullptr;
   // autotuned launch shape of each small batched tier, by log2 of the
   // tier's matrix count (-1: not tuned yet)
-  int8_t tuned_small[5][40];
+  int8_t tuned_small[binv::kSmallTierCount][40];
   // mixed precision workspace
   binv::DevBuf mx_w32, mx_ct32, mx_r32, mx_p32, mx_p64a, mx_p64b, mx_res, mx_xn, mx_part;
   // compensated residual: the split parts of A and of X, and their exponents

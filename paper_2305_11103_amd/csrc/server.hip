@@ -5,9 +5,10 @@
 // them in order while the server's HBM budget and in-flight limit allow, and
 // gives each admitted request its own device state (A, X and, for large
 // orders, the working panels of a context).  Work then proceeds in two ways:
-//  - requests of order <= kSmallMax are grouped: every scheduling round packs
+//  - requests of order <= kRoundMax are grouped: every scheduling round packs
 //    all admitted small requests into one buffer and inverts them with the
-//    register-resident batched kernels (one launch per size tier);
+//    batched kernels: the register-resident tiers up to kSmallMax (one launch
+//    per size tier), the swept step above (one launch per block step);
 //  - larger requests go to a pool of worker threads, each owning a library
 //    context and its own stream, so several sweeps overlap on the device.
 // A request that arrives while others are running is admitted as soon as
@@ -34,7 +35,7 @@
 
 namespace {
 
-constexpr int kSmallMax = 128;     // orders inverted by the register tiers of a round
+constexpr int kSmallMax = binv::kSmallMaxOrder;  // orders inverted by the register tiers of a round
 constexpr int kRoundMax = 256;     // orders grouped into rounds (above kSmallMax: swept steps)
 constexpr int kSweptBlock = 128;   // largest diagonal block of a swept step
 constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 3)
@@ -392,7 +393,7 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
   const int64_t cnt = (int64_t)reqs.size();
   std::vector<binv::SmallMat> mats(cnt);
   std::vector<int32_t> bounds;
-  std::vector<std::vector<int32_t>> tiers(5);
+  std::vector<std::vector<int32_t>> tiers(binv::kSmallTierCount);
   std::vector<int32_t> swept;  // request indices of the swept orders
   std::vector<int64_t> sw_off;  // their workspace offsets (elements)
   int64_t off = 0, sw_elems = 0;
@@ -417,8 +418,8 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
     off += (int64_t)m * m;
   }
   std::vector<int32_t> order;
-  int64_t first[5], count[5];
-  for (int t = 0; t < 5; ++t) {
+  int64_t first[binv::kSmallTierCount], count[binv::kSmallTierCount];
+  for (int t = 0; t < binv::kSmallTierCount; ++t) {
     first[t] = (int64_t)order.size();
     count[t] = (int64_t)tiers[t].size();
     order.insert(order.end(), tiers[t].begin(), tiers[t].end());
@@ -512,7 +513,7 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
       // the leaves record a zero pivot with a compare-and-swap on a zeroed word
       if (he == hipSuccess) he = hipMemsetAsync(s->rinfo.p, 0, sizeof(int32_t) * cnt, st);
     }
-    for (int t = 0; t < 5 && he == hipSuccess; ++t)
+    for (int t = 0; t < binv::kSmallTierCount && he == hipSuccess; ++t)
       he = binv::launch_small_tier(t, A, X, (const binv::SmallMat*)s->rmats.p, (const int32_t*)s->rorder.p + first[t],
                                    count[t], (const int32_t*)s->rbounds.p, (int32_t*)s->rinfo.p, st);
     for (size_t p = 0; p < step_jobs.size() && he == hipSuccess; ++p) {

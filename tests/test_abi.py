@@ -48,7 +48,7 @@ def test_tier_shape_table():
     for t, count in enumerate(binv.TIER_SHAPES):
         for v in range(count):
             rpl, cpw, nwv, sub = binv.batch_shape(t, v)
-            limit = (8, 16, 32, 64, 128)[t]
+            limit = binv.TIER_LIMITS[t]
             assert nwv * cpw >= limit and nwv * cpw <= 64 * rpl  # columns cover the tier, rows cover the columns
             assert 64 * nwv * sub <= 1024
         with pytest.raises(binv.BinvError):

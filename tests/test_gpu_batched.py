@@ -34,7 +34,7 @@ def check(A, X, bound):
 
 
 def test_every_tier_spd(gpu):
-    sizes = [1, 2, 5, 5, 8, 9, 16, 17, 31, 32, 33, 63, 64, 65, 100, 128, 129, 150, 200, 255, 256]
+    sizes = [1, 2, 5, 5, 8, 9, 16, 17, 31, 32, 33, 63, 64, 65, 100, 128, 129, 150, 191, 192, 193, 200, 255, 256]
     rng = np.random.default_rng(0)
     mats = [wl.spd_gram(m, 100 + i) for i, m in enumerate(sizes)]
     ks = [min(m, int(rng.integers(2, 5))) for m in sizes]
@@ -136,7 +136,7 @@ def test_autotuned_shapes_are_bitwise_equal_to_default(gpu):
     result equals the default plan's bit for bit, for every tier."""
     import torch
     from paper_2305_11103_amd import binv
-    sizes = [5] * 300 + [12] * 40 + [30] * 40 + [60] * 30 + [120] * 20 + [200] * 5
+    sizes = [5] * 300 + [12] * 40 + [30] * 40 + [60] * 30 + [120] * 20 + [170] * 8 + [200] * 5
     rng = np.random.default_rng(9)
     mats = [wl.spd_gram(m, 400 + i) for i, m in enumerate(sizes)]
     ks = [int(rng.integers(2, 5)) for _ in sizes]
@@ -149,7 +149,8 @@ def test_autotuned_shapes_are_bitwise_equal_to_default(gpu):
     X = torch.empty_like(A)
     chosen, ms, shapes = plan.tune(A, X, reps=2)
     assert all(0 <= c < len(shapes[t]) for t, c in enumerate(chosen))
-    for t in range(5):
+    assert len(chosen) == len(binv.TIER_SHAPES) == 6
+    for t in range(len(binv.TIER_SHAPES)):
         assert all(v > 0 for v in ms[t])
     torch.cuda.synchronize()
     assert torch.equal(X, X0)  # the tuner leaves a complete inversion behind

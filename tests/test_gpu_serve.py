@@ -33,17 +33,17 @@ def wait_all(srv, tickets, timeout=120.0):
 
 
 def in_round(n, prec, strict):
-    """Does the server run this request in a shared round?  Orders up to 128
-    always; 129..256 unless it is a mixed request honoured strictly (which
+    """Does the server run this request in a shared round?  Orders up to 192
+    always; 193..256 unless it is a mixed request honoured strictly (which
     starts from the FP32 sweep on a worker; its target 1e-10 is below that
     sweep's reach)."""
-    return n <= 128 or (n <= 256 and not (prec == "mixed" and strict))
+    return n <= 192 or (n <= 256 and not (prec == "mixed" and strict))
 
 
 def alone(A, n, prec, strict=True, full_check=True):
     """The same request through the single-matrix entry points, under the
     server's policy: a round's request through the batched API (register
-    tiers up to 128, swept steps of blocks of at most 128 above: the same
+    tiers up to 192, swept steps of blocks of at most 128 above: the same
     kernels and blocks), a worker's through invert_mixed with an FP64 start
     unless a mixed request is honoured strictly."""
     import torch
@@ -83,7 +83,7 @@ def test_mix_matches_alone_bitwise_and_meets_target(gpu, strict, full_check):
         assert info["converged"]
         assert times["total_ms"] >= times["queue_ms"] >= 0
         assert np.array_equal(X, alone(A, n, prec, strict, full_check)), (n, prec)
-        assert info["sampled"] == (0 if (n <= 128 or full_check) else info["sampled"])
+        assert info["sampled"] == (0 if (in_round(n, prec, strict) or full_check) else info["sampled"])
         if in_round(n, prec, strict):  # full residual measured on the device, no refinement needed here
             assert info["refine_steps"] == 0
             assert info["rho"] == pytest.approx(oracle.residual_stats(A, X)["rho"], rel=0.5, abs=1e-15)
@@ -211,9 +211,10 @@ def test_device_memory_stays_within_budget(gpu):
 
 
 def test_swept_round_groups_steps_and_isolates_failures(gpu):
-    """Orders 129..256 run in the server's rounds, block step by block step
-    in shared launches (one workgroup per request per step).  Every result is
-    bitwise the batched API's for the same order (same kernel, same blocks),
+    """Orders 129..256 run in the server's rounds: up to 192 in the register
+    tier, above that block step by block step in shared launches (one
+    workgroup per request per step).  Every result is bitwise the batched
+    API's for the same order (same kernels, same blocks),
     matches the oracle element by element and by residual, and a singular
     request in the round fails alone with its row."""
     from paper_2305_11103_amd import binv
