@@ -325,7 +325,7 @@ def bench_batched(args):
     loop_s = per_small * n_small + per_large * n_large
 
     # roofline: the phase with the most time is the dominant kernel.  The
-    # swept step (orders 129..256) is bound by HBM: its algorithmic traffic is
+    # swept step (orders above the register tiers') is bound by HBM: its algorithmic traffic is
     # reading and writing each matrix once per step, 16 m^2 bytes per matrix
     # and step (one step per diagonal block, blocks over 128 split in two).
     dom = max(phases, key=lambda p: timing[p][0])
@@ -336,7 +336,7 @@ def bench_batched(args):
     avg_ms = d_ms / max(d_cnt, 1)
     if dom == "schur":
         steps_bytes = sum(16.0 * m * m * sum((b + 127) // 128 for b in pb)
-                          for m, pb in zip(sizes, parts) if m > 128)
+                          for m, pb in zip(sizes, parts) if m > binv.TIER_LIMITS[-1])
         bytes_per_launch = steps_bytes * args.steps / max(d_cnt, 1)
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if d_ms > 0 else 0.0
         roof = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",

@@ -423,7 +423,7 @@ binv_status binv_batch_shape(int32_t tier, int32_t shape, int32_t out[4]);
  * inverted by the blockwise sweep on worker threads with their own streams,
  * so their work overlaps on the device: orders >= 4096 one at a time on the
  * first worker (with the lookahead schedule), the others on any worker
- * (BINV_SERVER_WORKERS in the environment sets the worker count, default 3).
+ * (BINV_SERVER_WORKERS in the environment sets the worker count, default 2).
  * Every request run by a worker ends with the FP64 residual check against its
  * target (binv_invert_mixed with BINV_F_SAMPLED_CHECK unless the server was
  * created with BINV_SERVER_FULL_CHECK) and is refined only when the check

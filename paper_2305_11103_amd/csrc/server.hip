@@ -38,7 +38,7 @@ namespace {
 constexpr int kSmallMax = binv::kSmallMaxOrder;  // orders inverted by the register tiers of a round
 constexpr int kRoundMax = 256;     // orders grouped into rounds (above kSmallMax: swept steps)
 constexpr int kSweptBlock = 128;   // largest diagonal block of a swept step
-constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 3)
+constexpr int kMaxWorkers = 8;     // concurrent large requests (BINV_SERVER_WORKERS, default 2)
 constexpr int kMaxRoundSmall = 65536;
 constexpr int64_t kBigN = 4096;    // orders served one at a time on worker 0
 constexpr double kFp32Reach = 1e-6;  // rho the FP32 sweep can meet without refinement
@@ -144,8 +144,11 @@ struct binv_server {
   uint64_t next_id = 1;
   bool stop = false;
   std::thread sched;
+  std::thread rounds;                // runs the rounds, apart from admission
+  std::condition_variable rcv;       // wakes the round thread
+  bool round_running = false;        // the round thread is using the round buffers
   std::vector<std::thread> workers;
-  int nworkers = 3;
+  int nworkers = 2;
   binv_ctx* wctx[kMaxWorkers] = {nullptr};
   // Device blocks of finished requests, kept for reuse by size class so that
   // collecting a result never calls hipFree (which waits for the whole
@@ -263,13 +266,13 @@ bool trim_workers_locked(binv_server* s, size_t need) {
 // the cache has a block of its class, a new block; cached blocks of other
 // classes and idle workers' workspace are released when that is the only way,
 // and, called from the scheduler thread (the only one that uses them), the
-// small-request round buffers too.
-bool make_room_locked(binv_server* s, Request* r, bool scheduler) {
+// small-request round buffers too, while no round is using them.
+bool make_room_locked(binv_server* s, Request* r) {
   const size_t need = r->ws + (pool_has(s, r->blk) ? 0 : r->blk);
   while (s->used + need > s->budget)
     if (!pool_evict_locked(s, r->blk)) break;
   if (s->used + need > s->budget) (void)trim_workers_locked(s, need);
-  if (s->used + need > s->budget && scheduler && s->round_held > 0) {
+  if (s->used + need > s->budget && !s->round_running && s->round_held > 0) {
     for (binv::DevBuf* d : {&s->rA, &s->rX, &s->rmats, &s->rorder, &s->rbounds, &s->rinfo, &s->rwork, &s->rtarget,
                             &s->rrho, &s->rsteps, &s->rsw, &s->rjobs})
       d->release();
@@ -337,6 +340,7 @@ bool fp32_start_of(const binv_server* s, const Request* r) {
 void route_locked(binv_server* s, Request* r) {
   if (in_round(r->n, fp32_start_of(s, r))) {
     s->small_ready.push_back(r);
+    s->rcv.notify_one();
     return;
   }
   if (r->n >= kBigN) s->big_ready.push_back(r);
@@ -356,7 +360,7 @@ void admit_locked(binv_server* s) {
       route_locked(s, r);
       continue;
     }
-    if (!make_room_locked(s, r, true)) break;  // wait until results are collected
+    if (!make_room_locked(s, r)) break;  // wait until results are collected
     const size_t nn = (size_t)r->n * (size_t)r->n;
     if (!request_alloc_locked(s, r)) break;
     if (copy_sync(s, r->dA, r->hostA.data(), sizeof(double) * nn, hipMemcpyHostToDevice) != hipSuccess) {
@@ -576,25 +580,38 @@ void run_small_round(binv_server* s, std::vector<Request*>& reqs) {
   }
 }
 
+// Admission runs on its own thread, so that a round waiting for the device
+// (its launches queue behind the workers' full-device grids) never holds up
+// the admission of the workers' next requests.
 void scheduler_main(binv_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     admit_locked(s);
-    if (!s->small_ready.empty()) {
-      std::vector<Request*> round;
-      round.swap(s->small_ready);
-      if ((int)round.size() > kMaxRoundSmall) {
-        s->small_ready.assign(round.begin() + kMaxRoundSmall, round.end());
-        round.resize(kMaxRoundSmall);
-      }
-      for (Request* r : round) r->state = Q_RUNNING;
-      lk.unlock();
-      run_small_round(s, round);
-      lk.lock();
-      continue;
-    }
     s->cv.wait_for(lk, std::chrono::microseconds(200));
+  }
+}
+
+// Rounds: everything admitted for the shared launches since the last round.
+void rounds_main(binv_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->rcv.wait(lk, [&] { return s->stop || !s->small_ready.empty(); });
+    if (s->small_ready.empty()) break;  // stopping, nothing left
+    std::vector<Request*> round;
+    round.swap(s->small_ready);
+    if ((int)round.size() > kMaxRoundSmall) {
+      s->small_ready.assign(round.begin() + kMaxRoundSmall, round.end());
+      round.resize(kMaxRoundSmall);
+    }
+    for (Request* r : round) r->state = Q_RUNNING;
+    s->round_running = true;
+    lk.unlock();
+    run_small_round(s, round);
+    lk.lock();
+    s->round_running = false;
+    s->cv.notify_all();  // the round's reservations are released: admission may proceed
   }
 }
 
@@ -700,6 +717,7 @@ binv_status binv_server_create(int device, size_t hbm_budget_bytes, int32_t max_
     s->wctx[w]->cu_mask = false;
   }
   s->sched = std::thread(scheduler_main, s);
+  s->rounds = std::thread(rounds_main, s);
   for (int w = 0; w < s->nworkers; ++w) s->workers.emplace_back(worker_main, s, w);
   *out = s;
   return BINV_OK;
@@ -732,7 +750,7 @@ binv_status binv_submit(binv_server* s, int64_t n, const double* A, int a_is_dev
       std::lock_guard<std::mutex> g(s->mu);
       // only when the queue is empty: a device input must not overtake
       // requests waiting for room
-      reserved = s->queue.empty() && make_room_locked(s, r, false) && request_alloc_locked(s, r);
+      reserved = s->queue.empty() && make_room_locked(s, r) && request_alloc_locked(s, r);
     }
     if (reserved) {
       hipError_t e = copy_sync(s, r->dA, A, sizeof(double) * nn, hipMemcpyDeviceToDevice);
@@ -848,10 +866,12 @@ binv_status binv_server_destroy(binv_server* s) {
     std::lock_guard<std::mutex> g(s->mu);
     s->stop = true;
     s->cv.notify_all();
+    s->rcv.notify_all();
     s->wcv.notify_all();
     s->dcv.notify_all();
   }
   if (s->sched.joinable()) s->sched.join();
+  if (s->rounds.joinable()) s->rounds.join();
   for (auto& t : s->workers)
     if (t.joinable()) t.join();
   for (auto& kv : s->all) {
