@@ -104,7 +104,8 @@ typedef enum {
                              both before the call's work ends.  With neither
                              this flag nor BINV_F_NO_LOOKAHEAD the lookahead is
                              used from n = 2048 up (below that the serial
-                             schedule measured as fast or faster); with both,
+                             schedule measured as fast or faster), and not with
+                             BINV_F_PIVOT (serial measured faster); with both,
                              BINV_F_NO_LOOKAHEAD wins.  Results are bitwise
                              identical either way. */
 

@@ -39,6 +39,10 @@ constexpr int64_t kLookaheadMinN = 2048;
 bool use_lookahead(uint32_t flags, int64_t n) {
   if (flags & BINV_F_NO_LOOKAHEAD) return false;
   if (flags & BINV_F_LOOKAHEAD) return true;
+  // the pivoted sweep's selection chain does not hide under the trailing
+  // update, and beside it both slow down: serial measured 2% faster at
+  // n = 8192 and 16384
+  if (flags & BINV_F_PIVOT) return false;
   return n >= kLookaheadMinN;
 }
 

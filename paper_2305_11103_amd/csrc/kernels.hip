@@ -1238,13 +1238,17 @@ __device__ __forceinline__ int tourn_search(const double (&x)[RPL], const bool (
 
 // One tournament node per workgroup: 4 waves, lane l holding candidates
 // l + 64 h (h < 4), wave v holding strip columns [16 v, 16 v + 16).
-__global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
+// CPW strip columns per wave, 64 / CPW waves: fewer columns per wave shorten
+// each wave's share of a column step (its updates and pivot-row reads).
+template <int CPW>
+__global__ void __launch_bounds__(64 * (64 / CPW)) k_tourn_node(TournArgs a) {
   // the selection gates the next step's row panel and runs beside the
   // trailing update: its waves issue ahead of the update's on shared CUs
   __builtin_amdgcn_s_setprio(3);
-  constexpr int RPL = kTournRows / 64, CPW = 16;
+  constexpr int RPL = kTournRows / 64, NW = 64 / CPW;
+  static_assert(NW * CPW == 64 && NW >= kTournArity && 64 * NW >= kTournRows, "waves must cover the strip and the candidates");
   __shared__ int cand[kTournRows];
-  __shared__ int wcount[4];
+  __shared__ int wcount[NW];
   __shared__ double colbuf[2][kTournRows];
   __shared__ int s_r[2];
   __shared__ double s_pv[2];
@@ -1256,17 +1260,17 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
   int row = -1;
   if (a.is_leaf) {
     const int64_t r = a.o + node * kTournRows + tid;
-    if (r < a.n && a.used[r] == 0) row = (int)r;
+    if (tid < kTournRows && r < a.n && a.used[r] == 0) row = (int)r;
   } else {
     const int64_t child = node * kTournArity + (tid >> 6);
-    if (child < a.nin) row = a.in[child * 64 + lane];
+    if ((tid >> 6) < kTournArity && child < a.nin) row = a.in[child * 64 + lane];
   }
   const unsigned long long mk = __ballot(row >= 0);
   if (lane == 0) wcount[wave] = __popcll(mk);
   __syncthreads();
   int before = 0, nc = 0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
+  for (int v = 0; v < NW; ++v) {
     before += (v < wave) ? wcount[v] : 0;
     nc += wcount[v];
   }
@@ -1274,11 +1278,10 @@ __global__ void __launch_bounds__(256) k_tourn_node(TournArgs a) {
   __syncthreads();
 
   const int w = a.w;
-  // row half h of this wave's 16 columns (a vector, so that the next
+  // row half h of this wave's CPW columns (a vector, so that the next
   // column's slot, a uniform index, is one indexed register move)
-  typedef double v16d __attribute__((ext_vector_type(16)));
-  static_assert(CPW == 16, "one 16-wide vector per row half");
-  v16d v[RPL];
+  typedef double vcd __attribute__((ext_vector_type(CPW)));
+  vcd v[RPL];
   bool used[RPL];
 #pragma unroll
   for (int h = 0; h < RPL; ++h) {
@@ -1491,7 +1494,9 @@ __global__ void __launch_bounds__(1024) k_unpermute_cols(double* W, int64_t ldw,
 // ---- launchers ----
 hipError_t launch_tourn_level(const TournArgs& a, int64_t nodes, hipStream_t s) {
   if (nodes <= 0 || a.w <= 0 || a.w > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tourn_node, dim3((unsigned)nodes), dim3(256), 0, s, a);
+  // 8 waves of 8 columns (measured: pivoted sweep 87 against 96 ms at
+  // n = 8192 for 4 waves of 16, 88 for 16 waves of 4)
+  hipLaunchKernelGGL(k_tourn_node<8>, dim3((unsigned)nodes), dim3(512), 0, s, a);
   return hipGetLastError();
 }
 
