@@ -1307,12 +1307,12 @@ __global__ void __launch_bounds__(64 * (64 / CPW)) k_tourn_node(TournArgs a) {
       s_pv[0] = pv;
     }
   }
-  // Per column c: the pivot row's values in this wave's columns (read from
-  // lane r % 64 of row half r / 64, a uniform choice), the multipliers, then
-  // column c + 1 by its owner wave and its pivot search, then every other
-  // slot.  Columns up to c are never read again, so their slots are updated
-  // too (the rows' values there no longer matter) and every register index is
-  // a constant; only the next column's slot (a uniform index) is chosen at run
+  // Per column c: the multipliers, then column c + 1 by its owner wave and
+  // its pivot search, then every slot of every wave with the pivot row's
+  // values (read from lane r % 64 of row half r / 64, a uniform choice).
+  // Columns up to c are never read again, so their slots are updated too (the
+  // rows' values there no longer matter) and every register index is a
+  // constant; only the next column's slot (a uniform index) is chosen at run
   // time.
   int got = 0, zero = -1;
   for (int c = 0; c < w; ++c) {
@@ -1327,14 +1327,6 @@ __global__ void __launch_bounds__(64 * (64 / CPW)) k_tourn_node(TournArgs a) {
     const double q = pv != 0.0 ? 1.0 / pv : 0.0;
     const int rl = __builtin_amdgcn_readfirstlane(r & 63);
     const int rh = __builtin_amdgcn_readfirstlane(r >> 6);
-    double sp[CPW];
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      double t = v[0][j];
-#pragma unroll
-      for (int h = 1; h < RPL; ++h) t = (h == rh) ? v[h][j] : t;
-      sp[j] = readlane_f64(t, rl);
-    }
     double f[RPL];
 #pragma unroll
     for (int h = 0; h < RPL; ++h) {
@@ -1347,14 +1339,15 @@ __global__ void __launch_bounds__(64 * (64 / CPW)) k_tourn_node(TournArgs a) {
     const bool nowner = (cn < w) && (cn / CPW == wave);
     const int sn = cn % CPW;
     if (nowner) {
+      // the pivot row's value in column c + 1 alone, read first: the search
+      // does not wait for the rest of the row
+      double t = v[0][sn];
+#pragma unroll
+      for (int h = 1; h < RPL; ++h) t = (h == rh) ? v[h][sn] : t;
+      const double pj = readlane_f64(t, rl);
       double x[RPL];
 #pragma unroll
-      for (int h = 0; h < RPL; ++h) {
-        double pj = 0.0;
-#pragma unroll
-        for (int j = 0; j < CPW; ++j) pj = (j == sn) ? sp[j] : pj;
-        x[h] = fma(-f[h], pj, v[h][sn]);
-      }
+      for (int h = 0; h < RPL; ++h) x[h] = fma(-f[h], pj, v[h][sn]);
       double pv2;
       const int r2 = tourn_search<RPL>(x, used, pv2);
 #pragma unroll
@@ -1364,10 +1357,16 @@ __global__ void __launch_bounds__(64 * (64 / CPW)) k_tourn_node(TournArgs a) {
         s_pv[buf ^ 1] = pv2;
       }
     }
+    // the pivot row's values in this wave's columns, then every slot
 #pragma unroll
-    for (int j = 0; j < CPW; ++j)
+    for (int j = 0; j < CPW; ++j) {
+      double t = v[0][j];
 #pragma unroll
-      for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp[j], v[h][j]);
+      for (int h = 1; h < RPL; ++h) t = (h == rh) ? v[h][j] : t;
+      const double sp = readlane_f64(t, rl);
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) v[h][j] = fma(-f[h], sp, v[h][j]);
+    }
   }
   __syncthreads();
   if (tid < 64) {
