@@ -164,6 +164,22 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
     const int s = bs[(v + 1) << l] - u0;
     return T[toff[l][v] + (r - u0) * s + (c - u0)];
   };
+  // The square holding the level-l unit of row (or column) x: element (i, j)
+  // of the unit is at base[i * ld + j] for the unit's rows and columns i, j
+  // (global indices).  l = 0 names the input matrix itself.  A product's
+  // inner index stays inside one unit, so its terms take the unit's square
+  // once instead of looking up the unit per term.
+  struct Sq {
+    const double* base;
+    int ld;
+  };
+  auto square = [&](int l, int x) -> Sq {
+    if (l == 0) return Sq{M, m};
+    const int v = rb[x] >> l;
+    const int u0 = bs[v << l];
+    const int s = bs[(v + 1) << l] - u0;
+    return Sq{T + toff[l][v] - (int64_t)u0 * s - u0, s};
+  };
 
   const int ns = 2 * nk - 1;
   for (int step = 1; step <= ns; ++step) {
@@ -182,8 +198,12 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
         const int v = br >> l;
         const int k0 = hr == 0 ? bs[v << l] : bs[(v << l) + (1 << (l - 1))];
         const int k1 = hr == 0 ? bs[(v << l) + (1 << (l - 1))] : bs[(v + 1) << l];
+        // (k, c) lie in one level-src unit (src > l, or the input)
+        const Sq q = square(src, c);
+        const double* sc = q.base + c;
+        const double* mi = Minv + r * MMAX;
         double acc = 0.0;
-        for (int k = k0; k < k1; ++k) acc = fma(Minv[r * MMAX + k], src_el(src, k, c), acc);
+        for (int k = k0; k < k1; ++k) acc = fma(mi[k], sc[(int64_t)k * q.ld], acc);
         t_at(l, r, c) = -acc;
       }
       __syncthreads();
@@ -196,8 +216,13 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
         const int v = br >> l;
         const int k0 = hr == 1 ? bs[v << l] : bs[(v << l) + (1 << (l - 1))];
         const int k1 = hr == 1 ? bs[(v << l) + (1 << (l - 1))] : bs[(v + 1) << l];
-        double acc = src_el(src, r, c);
-        for (int k = k0; k < k1; ++k) acc = fma(src_el(src, r, k), t_at(l, k, c), acc);
+        // (r, k) in one level-src unit, (k, c) in the level-l unit
+        const Sq qs = square(src, r);
+        const Sq qt = square(l, c);
+        const double* sr = qs.base + (int64_t)r * qs.ld;
+        const double* tc = qt.base + c;
+        double acc = sr[c];
+        for (int k = k0; k < k1; ++k) acc = fma(sr[k], tc[(int64_t)k * qt.ld], acc);
         t_at(l, r, c) = acc;
       }
       __syncthreads();
@@ -229,8 +254,10 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
           // X12 = R S_A^-1 (k over D), X21 = L S_D^-1 (k over A)
           const int k0 = hr == 0 ? bs[(v << l) + (1 << (l - 1))] : bs[v << l];
           const int k1 = hr == 0 ? bs[(v + 1) << l] : bs[(v << l) + (1 << (l - 1))];
+          const Sq qt = square(l, r);
+          const double* tr = qt.base + (int64_t)r * qt.ld;
           double acc = 0.0;
-          for (int k = k0; k < k1; ++k) acc = fma(t_at(l, r, k), Minv[k * MMAX + c], acc);
+          for (int k = k0; k < k1; ++k) acc = fma(tr[k], Minv[k * MMAX + c], acc);
           Minv[r * MMAX + c] = acc;
         }
         __syncthreads();
