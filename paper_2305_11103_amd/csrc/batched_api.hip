@@ -95,8 +95,9 @@ struct binv_batch {
   // the paper's level scheme (binv_invert_batched_levels): matrices grouped
   // by tier (orders <= 8, 16, 32, 64), formed on its first call
   bool lvl_ready = false;
-  int64_t lvl_first[4] = {0}, lvl_count[4] = {0};
-  double lvl_flops[4] = {0};  // the scheme's own flops per tier
+  int64_t lvl_first[binv::kLevelClasses] = {0}, lvl_count[binv::kLevelClasses] = {0};
+  size_t lvl_lds[binv::kLevelClasses] = {0};    // each class launch's dynamic LDS (doubles)
+  double lvl_flops[binv::kLevelClasses] = {0};  // the scheme's own flops per class
   void* d_lvl_order = nullptr;
 };
 
@@ -427,21 +428,22 @@ binv_status binv_invert_batched_levels(binv_batch* b, const double* A, double* X
     if (a0 < x1 && x0 < a1) return bfail(BINV_E_INVALID, "A and X overlap without being the same buffer");
   }
   if (!b->lvl_ready) {
-    std::vector<int32_t> tiers[4];
+    constexpr int NC = binv::kLevelClasses;
+    std::vector<int32_t> classes[NC];
     for (int64_t i = 0; i < b->count; ++i) {
       const int mi = b->m[i];
       const int bi = b->bnd_index[i];
       const int nk = b->bnd_index[i + 1] - bi - 1;
       const std::string at = " (matrix " + std::to_string(i) + ")";
-      if (mi > binv::level_tier_limit(3)) return bfail(BINV_E_INVALID, "the level scheme takes orders <= 64" + at);
+      if (mi > binv::level_class_limit(NC - 1)) return bfail(BINV_E_INVALID, "the level scheme takes orders <= 64" + at);
       if (nk & (nk - 1)) return bfail(BINV_E_INVALID, "the block count must be a power of two" + at);
       for (int j = 0; j < nk; ++j)
         if (b->bounds_host[bi + j + 1] - b->bounds_host[bi + j] > 4)
           return bfail(BINV_E_INVALID, "the level scheme's diagonal blocks have orders <= 4" + at);
-      int t = 0;
-      while (mi > binv::level_tier_limit(t)) ++t;
-      // the provisional sets: every level-l unit's square
-      size_t need = 0;
+      int c = 0;
+      while (mi > binv::level_class_limit(c)) ++c;
+      // M_inv and the provisional sets: every level-l unit's square
+      size_t need = (size_t)mi * mi;
       double fl = 0.0;
       for (int j = 0; j < nk; ++j) {
         const double bj = b->bounds_host[bi + j + 1] - b->bounds_host[bi + j];
@@ -458,28 +460,29 @@ binv_status binv_invert_batched_levels(binv_batch* b, const double* A, double* X
           const double na = uh - u0, nd = u1 - uh;
           fl += 6.0 * na * nd * (na + nd) * (double)(nk >> l);
         }
-      if (need > binv::level_tier_tmax(t))
-        return bfail(BINV_E_INVALID, "the partition's provisional sets exceed the tier's on-chip store" + at);
-      tiers[t].push_back((int32_t)i);
-      b->lvl_flops[t] += fl;
+      if (need > binv::kLevelLdsDoubles)
+        return bfail(BINV_E_INVALID, "the inverse and provisional sets exceed the on-chip store" + at);
+      classes[c].push_back((int32_t)i);
+      b->lvl_flops[c] += fl;
+      b->lvl_lds[c] = std::max(b->lvl_lds[c], need);
     }
     std::vector<int32_t> order;
-    for (int t = 0; t < 4; ++t) {
-      b->lvl_first[t] = (int64_t)order.size();
-      b->lvl_count[t] = (int64_t)tiers[t].size();
-      order.insert(order.end(), tiers[t].begin(), tiers[t].end());
+    for (int c = 0; c < NC; ++c) {
+      b->lvl_first[c] = (int64_t)order.size();
+      b->lvl_count[c] = (int64_t)classes[c].size();
+      order.insert(order.end(), classes[c].begin(), classes[c].end());
     }
     binv_status st = upload(order, &b->d_lvl_order);
     if (st != BINV_OK) return st;
     b->lvl_ready = true;
   }
   hipStream_t s = (hipStream_t)stream;
-  for (int t = 0; t < 4; ++t) {
+  for (int c = 0; c < binv::kLevelClasses; ++c) {
     binv::PhaseTimer tm(b->ctx, 0, BINV_PHASE_SMALL, s);
-    if (tm.on()) tm.flops = b->lvl_flops[t];
-    BHIP(binv::launch_level_tier(t, A, X, (const binv::SmallMat*)b->d_mats,
-                                 (const int32_t*)b->d_lvl_order + b->lvl_first[t], b->lvl_count[t],
-                                 (const int32_t*)b->d_bounds, d_info, s));
+    if (tm.on()) tm.flops = b->lvl_flops[c];
+    BHIP(binv::launch_level_class(c, A, X, (const binv::SmallMat*)b->d_mats,
+                                  (const int32_t*)b->d_lvl_order + b->lvl_first[c], b->lvl_count[c], b->lvl_lds[c],
+                                  (const int32_t*)b->d_bounds, d_info, s));
   }
   if (flags & BINV_F_SYNC) BHIP(hipStreamSynchronize(s));
   return BINV_OK;

@@ -206,12 +206,16 @@ hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats,
                                int32_t* steps, hipStream_t s);
 
 // levels.hip: the paper's parallel algorithm (§5) on packed small matrices,
-// one workgroup per matrix; tier t takes orders <= level_tier_limit(t) (8, 16,
-// 32, 64) with provisional sets of at most level_tier_tmax(t) doubles.
-int level_tier_limit(int t);
-size_t level_tier_tmax(int t);
-hipError_t launch_level_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
-                             int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s);
+// one workgroup per matrix.  Class c takes orders <= level_class_limit(c)
+// (8, 16, 32, 40, 48, 59, 64); a launch's dynamic LDS is lds_doubles (the
+// largest m^2 plus provisional sets of its matrices), at most
+// kLevelLdsDoubles.
+constexpr int kLevelClasses = 7;
+constexpr size_t kLevelLdsDoubles = 19968;  // 156 KB of the CU's 160
+int level_class_limit(int c);
+hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat* mats, const int32_t* order,
+                              int64_t count, size_t lds_doubles, const int32_t* bounds, int32_t* info,
+                              hipStream_t s);
 
 // binv_api.hip: records the thread-local message returned by binv_last_error
 void set_error(const std::string& msg);

@@ -23,6 +23,14 @@
 // operations are independent across units and output elements, so the
 // workgroup's threads share them; a barrier separates dependent phases, the
 // role the paper gives stepid in its thread barriers.
+//
+// Work sharing: each row of the matrix has a group of threads, and in every
+// product phase a row's outputs form one contiguous column range (the other
+// half, or its own half, of the row's unit at the phase's level), so a group
+// walks only the outputs that exist.  The closed-form inverses take one
+// thread per block element.  A launch's LDS is the largest
+// m^2 + |T_1..T_K| of its matrices, and orders are launched in classes whose
+// LDS lets 4, 3, 2 or 1 workgroups share a CU.
 #include <hip/hip_runtime.h>
 
 #include "binv_internal.h"
@@ -31,112 +39,93 @@ namespace binv {
 
 namespace {
 
-// det of the b x b (b <= 4) matrix a (row stride 4) by Laplace expansion
-// along the first row.
 __device__ __forceinline__ double det2(double a, double b, double c, double d) { return a * d - b * c; }
 
-__device__ __forceinline__ double det3(const double (&a)[4][4], int r0, int r1, int r2, int c0, int c1, int c2) {
-  return a[r0][c0] * det2(a[r1][c1], a[r1][c2], a[r2][c1], a[r2][c2]) -
-         a[r0][c1] * det2(a[r1][c0], a[r1][c2], a[r2][c0], a[r2][c2]) +
-         a[r0][c2] * det2(a[r1][c0], a[r1][c1], a[r2][c0], a[r2][c1]);
+// det of the 3 x 3 matrix with elements e(x, y), expanded along its first row
+template <class E>
+__device__ __forceinline__ double det3(E e) {
+  return e(0, 0) * det2(e(1, 1), e(1, 2), e(2, 1), e(2, 2)) - e(0, 1) * det2(e(1, 0), e(1, 2), e(2, 0), e(2, 2)) +
+         e(0, 2) * det2(e(1, 0), e(1, 1), e(2, 0), e(2, 1));
 }
 
-// Closed-form inverse (adjugate over determinant) of a block of order b <= 4
-// into inv; returns false when the determinant is exactly zero.
-__device__ bool leaf_closed_form(const double (&a)[4][4], int b, double (&inv)[4][4]) {
+// Element (i, k) of the closed-form inverse (adjugate over determinant) of
+// the block of order b <= 4 whose element (r, c) is el(r, c): the cofactor of
+// (k, i) over the determinant, which is expanded along the block's first row.
+// *d receives the determinant (every element's thread computes the same one;
+// a zero determinant leaves the element undefined).
+template <class El>
+__device__ double leaf_element(El el, int b, int i, int k, double* d) {
   if (b == 1) {
-    if (a[0][0] == 0.0) return false;
-    inv[0][0] = 1.0 / a[0][0];
-    return true;
+    *d = el(0, 0);
+    return 1.0 / el(0, 0);
   }
   if (b == 2) {
-    const double d = det2(a[0][0], a[0][1], a[1][0], a[1][1]);
-    if (d == 0.0) return false;
-    inv[0][0] = a[1][1] / d;
-    inv[0][1] = -a[0][1] / d;
-    inv[1][0] = -a[1][0] / d;
-    inv[1][1] = a[0][0] / d;
-    return true;
-  }
-  // cofactor C[i][j] = (-1)^(i+j) det(a without row i and column j);
-  // inv[j][i] = C[i][j] / det
-  int rows[4][3], cols[4][3];
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    int q = 0;
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-      if (y != x) {
-        rows[x][q] = y;
-        cols[x][q] = y;
-        ++q;
-      }
+    const double dd = det2(el(0, 0), el(0, 1), el(1, 0), el(1, 1));
+    *d = dd;
+    // [[a11, -a01], [-a10, a00]] / d
+    const double num = i == k ? el(1 - i, 1 - i) : -el(i, k);
+    return num / dd;
   }
   if (b == 3) {
-    double cof[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int i0 = i == 0 ? 1 : 0, i1 = i == 2 ? 1 : 2;
-        const int j0 = j == 0 ? 1 : 0, j1 = j == 2 ? 1 : 2;
-        const double m = det2(a[i0][j0], a[i0][j1], a[i1][j0], a[i1][j1]);
-        cof[i][j] = ((i + j) & 1) ? -m : m;
-      }
-    const double d = a[0][0] * cof[0][0] + a[0][1] * cof[0][1] + a[0][2] * cof[0][2];
-    if (d == 0.0) return false;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) inv[j][i] = cof[i][j] / d;
-    return true;
+    // cofactor (p, q): the signed det of the rows other than p and the
+    // columns other than q, in ascending order
+    auto cof = [&](int p, int q) {
+      const int p0 = p == 0 ? 1 : 0, p1 = p == 2 ? 1 : 2;
+      const int q0 = q == 0 ? 1 : 0, q1 = q == 2 ? 1 : 2;
+      const double mnr = det2(el(p0, q0), el(p0, q1), el(p1, q0), el(p1, q1));
+      return ((p + q) & 1) ? -mnr : mnr;
+    };
+    const double dd = el(0, 0) * cof(0, 0) + el(0, 1) * cof(0, 1) + el(0, 2) * cof(0, 2);
+    *d = dd;
+    return cof(k, i) / dd;
   }
-  double cof[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double m = det3(a, rows[i][0], rows[i][1], rows[i][2], cols[j][0], cols[j][1], cols[j][2]);
-      cof[i][j] = ((i + j) & 1) ? -m : m;
-    }
-  const double d = a[0][0] * cof[0][0] + a[0][1] * cof[0][1] + a[0][2] * cof[0][2] + a[0][3] * cof[0][3];
-  if (d == 0.0) return false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) inv[j][i] = cof[i][j] / d;
-  return true;
+  auto cof = [&](int p, int q) {
+    const int p0 = p == 0 ? 1 : 0, p1 = p <= 1 ? 2 : 1, p2 = p <= 2 ? 3 : 2;
+    const int q0 = q == 0 ? 1 : 0, q1 = q <= 1 ? 2 : 1, q2 = q <= 2 ? 3 : 2;
+    const double mnr = det3([&](int x, int y) {
+      return el(x == 0 ? p0 : x == 1 ? p1 : p2, y == 0 ? q0 : y == 1 ? q1 : q2);
+    });
+    return ((p + q) & 1) ? -mnr : mnr;
+  };
+  const double dd = el(0, 0) * cof(0, 0) + el(0, 1) * cof(0, 1) + el(0, 2) * cof(0, 2) + el(0, 3) * cof(0, 3);
+  *d = dd;
+  return cof(k, i) / dd;
 }
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
 }  // namespace
 
-// MMAX: largest order of the launch's matrices; NT threads.  Dynamic LDS:
-// M_inv (MMAX^2 doubles, row stride MMAX) then the compact provisional sets
-// (tmax doubles, checked on the host).
-template <int MMAX, int NT>
-__global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ A, double* __restrict__ X,
+// MMAX: largest order of the launch's matrices; NT threads; at least WPE
+// waves per SIMD (bounds the registers so that the class's workgroups fit a
+// CU together).  Dynamic LDS:
+// M_inv (m^2 doubles, row stride m) then the compact provisional sets (sized
+// on the host from the launch's partitions).
+template <int MMAX, int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) k_level_scheme(const double* __restrict__ A, double* __restrict__ X,
                                                      const SmallMat* __restrict__ mats,
                                                      const int32_t* __restrict__ order,
                                                      const int32_t* __restrict__ bounds, int32_t* __restrict__ info) {
   constexpr int KMAX = ilog2c(MMAX);
+  constexpr int UMAX = MMAX / 2 > 0 ? MMAX / 2 : 1;  // units per level (levels >= 1)
   extern __shared__ double lds[];
-  double* Minv = lds;
-  double* T = lds + MMAX * MMAX;
   __shared__ int bs[MMAX + 1];          // first row of each diagonal block, then m
   __shared__ int rb[MMAX];              // diagonal block of each row
-  __shared__ int toff[KMAX + 1][MMAX];  // offset of level-l unit v's square in T
+  __shared__ int toff[KMAX + 1][UMAX];  // offset of level-l unit v's square in T
   __shared__ int sing;
 
   const SmallMat mt = mats[order[blockIdx.x]];
   const int m = mt.m, nk = mt.nb;
   const double* __restrict__ M = A + mt.off;
+  double* Minv = lds;
+  double* T = lds + m * m;
   const int tid = threadIdx.x;
+  for (int j = tid; j <= nk; j += NT) bs[j] = bounds[mt.bnd + j];
+  if (tid == 0) sing = 0x7fffffff;
+  __syncthreads();
+  for (int j = tid; j < nk; j += NT)
+    for (int r = bs[j]; r < bs[j + 1]; ++r) rb[r] = j;
   if (tid == 0) {
-    for (int j = 0; j <= nk; ++j) bs[j] = bounds[mt.bnd + j];
-    for (int j = 0; j < nk; ++j)
-      for (int r = bs[j]; r < bs[j + 1]; ++r) rb[r] = j;
     int off = 0;
     for (int l = 1; (1 << l) <= nk; ++l)
       for (int v = 0; v < (nk >> l); ++v) {
@@ -144,31 +133,17 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
         const int s = bs[(v + 1) << l] - bs[v << l];
         off += s * s;
       }
-    sing = 0x7fffffff;
   }
   __syncthreads();
 
-  // element (r, c) of a step's source: the input matrix (src 0) or the Schur
-  // complements held in T_src (r and c lie in one level-src unit)
-  auto src_el = [&](int src, int r, int c) -> double {
-    if (src == 0) return M[r * m + c];
-    const int v = rb[r] >> src;
-    const int u0 = bs[v << src];
-    const int s = bs[(v + 1) << src] - u0;
-    return T[toff[src][v] + (r - u0) * s + (c - u0)];
-  };
-  // the slot of (r, c) in T_l (r and c in one level-l unit)
-  auto t_at = [&](int l, int r, int c) -> double& {
-    const int v = rb[r] >> l;
-    const int u0 = bs[v << l];
-    const int s = bs[(v + 1) << l] - u0;
-    return T[toff[l][v] + (r - u0) * s + (c - u0)];
-  };
+  // Each row r < m has G threads (lane g of them).
+  const int G = NT / m;
+  const int r = tid / G, g = tid - r * G;
+  const bool row = r < m;
+
   // The square holding the level-l unit of row (or column) x: element (i, j)
   // of the unit is at base[i * ld + j] for the unit's rows and columns i, j
-  // (global indices).  l = 0 names the input matrix itself.  A product's
-  // inner index stays inside one unit, so its terms take the unit's square
-  // once instead of looking up the unit per term.
+  // (global indices).  l = 0 names the input matrix itself.
   struct Sq {
     const double* base;
     int ld;
@@ -180,6 +155,24 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
     const int s = bs[(v + 1) << l] - u0;
     return Sq{T + toff[l][v] - (int64_t)u0 * s - u0, s};
   };
+  // Row r's level-l unit (l >= 1): its rows u0..u1-1, halves A = u0..uh-1
+  // and D = uh..u1-1, and its square in T_l (element (i, j) at sq[i * s + j]).
+  struct Unit {
+    int u0, uh, u1, s;
+    bool inA;
+    double* sq;
+  };
+  auto unit = [&](int l) -> Unit {
+    const int v = rb[r] >> l;
+    Unit u;
+    u.u0 = bs[v << l];
+    u.uh = bs[(v << l) + (1 << (l - 1))];
+    u.u1 = bs[(v + 1) << l];
+    u.s = u.u1 - u.u0;
+    u.inA = r < u.uh;
+    u.sq = T + toff[l][v] - (int64_t)u.u0 * u.s - u.u0;
+    return u;
+  };
 
   const int ns = 2 * nk - 1;
   for (int step = 1; step <= ns; ++step) {
@@ -188,118 +181,124 @@ __global__ void __launch_bounds__(NT) k_level_scheme(const double* __restrict__ 
     const int src = hi ? __builtin_ctz(hi) + z : 0;  // T_(p-1), or the input
     if (z > 1) {
       const int l = z - 1;
-      // → and ←: R = -A^-1 B (rows of A, columns of D), L = -D^-1 C
-      for (int idx = tid; idx < m * m; idx += NT) {
-        const int r = idx / m, c = idx - (idx / m) * m;
-        const int br = rb[r], bc = rb[c];
-        if ((br >> l) != (bc >> l)) continue;
-        const int hr = (br >> (l - 1)) & 1, hc = (bc >> (l - 1)) & 1;
-        if (hr == hc) continue;
-        const int v = br >> l;
-        const int k0 = hr == 0 ? bs[v << l] : bs[(v << l) + (1 << (l - 1))];
-        const int k1 = hr == 0 ? bs[(v << l) + (1 << (l - 1))] : bs[(v + 1) << l];
-        // (k, c) lie in one level-src unit (src > l, or the input)
-        const Sq q = square(src, c);
-        const double* sc = q.base + c;
-        const double* mi = Minv + r * MMAX;
-        double acc = 0.0;
-        for (int k = k0; k < k1; ++k) acc = fma(mi[k], sc[(int64_t)k * q.ld], acc);
-        t_at(l, r, c) = -acc;
+      if (row) {
+        // → and ←: R = -A^-1 B (rows of A, columns of D), L = -D^-1 C; the
+        // sum runs over the row's own half, whose inverse M_inv holds
+        const Unit u = unit(l);
+        const int c0 = u.inA ? u.uh : u.u0, c1 = u.inA ? u.u1 : u.uh;
+        const int k0 = u.inA ? u.u0 : u.uh, k1 = u.inA ? u.uh : u.u1;
+        // B and C lie in the row's level-src unit (src > l), or the input
+        const Sq q = square(src, r);
+        const double* mi = Minv + r * m;
+        double* out = u.sq + (int64_t)r * u.s;
+        for (int c = c0 + g; c < c1; c += G) {
+          const double* sc = q.base + c;
+          double acc = 0.0;
+          for (int k = k0; k < k1; ++k) acc = fma(mi[k], sc[(int64_t)k * q.ld], acc);
+          out[c] = -acc;
+        }
       }
       __syncthreads();
-      // ∼: S_A = D + C R (rows and columns of D), S_D = A + B L (of A)
-      for (int idx = tid; idx < m * m; idx += NT) {
-        const int r = idx / m, c = idx - (idx / m) * m;
-        const int br = rb[r], bc = rb[c];
-        if ((br >> (l - 1)) != (bc >> (l - 1))) continue;
-        const int hr = (br >> (l - 1)) & 1;
-        const int v = br >> l;
-        const int k0 = hr == 1 ? bs[v << l] : bs[(v << l) + (1 << (l - 1))];
-        const int k1 = hr == 1 ? bs[(v << l) + (1 << (l - 1))] : bs[(v + 1) << l];
-        // (r, k) in one level-src unit, (k, c) in the level-l unit
-        const Sq qs = square(src, r);
-        const Sq qt = square(l, c);
-        const double* sr = qs.base + (int64_t)r * qs.ld;
-        const double* tc = qt.base + c;
-        double acc = sr[c];
-        for (int k = k0; k < k1; ++k) acc = fma(sr[k], tc[(int64_t)k * qt.ld], acc);
-        t_at(l, r, c) = acc;
+      if (row) {
+        // ∼: S_A = D + C R (rows and columns of D), S_D = A + B L (of A);
+        // the sum runs over the other half
+        const Unit u = unit(l);
+        const int c0 = u.inA ? u.u0 : u.uh, c1 = u.inA ? u.uh : u.u1;
+        const int k0 = u.inA ? u.uh : u.u0, k1 = u.inA ? u.u1 : u.uh;
+        const Sq q = square(src, r);
+        const double* sr = q.base + (int64_t)r * q.ld;
+        double* out = u.sq + (int64_t)r * u.s;
+        for (int c = c0 + g; c < c1; c += G) {
+          const double* tc = u.sq + c;
+          double acc = sr[c];
+          for (int k = k0; k < k1; ++k) acc = fma(sr[k], tc[(int64_t)k * u.s], acc);
+          out[c] = acc;
+        }
       }
       __syncthreads();
     } else {
-      // ◊: every diagonal block of the source, closed form, into M_inv
-      for (int j = tid; j < nk; j += NT) {
-        const int o = bs[j], b = bs[j + 1] - bs[j];
-        double a[4][4], inv[4][4] = {};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) a[i][k] = (i < b && k < b) ? src_el(src, o + i, o + k) : 0.0;
+      // ◊: every diagonal block of the source, closed form, into M_inv, one
+      // thread per block element
+      for (int slot = tid; slot < nk * 16; slot += NT) {
+        const int j = slot >> 4, i = (slot >> 2) & 3, k = slot & 3;
+        const int o = bs[j], b = bs[j + 1] - o;
+        if (i >= b || k >= b) continue;
+        const Sq q = square(src, o);
+        const double* blk = q.base + (int64_t)o * q.ld + o;
+        const int ld = q.ld;
+        double d;
+        const double x = leaf_element([&](int y, int w) { return blk[(int64_t)y * ld + w]; }, b, i, k, &d);
         // a zero determinant: the earliest step, then the lowest block, wins
-        if (!leaf_closed_form(a, b, inv)) atomicMin(&sing, step * 65536 + o + 1);
-        for (int i = 0; i < b; ++i)
-          for (int k = 0; k < b; ++k) Minv[(o + i) * MMAX + o + k] = inv[i][k];
+        if (d == 0.0) {
+          if (i == 0 && k == 0) atomicMin(&sing, step * 65536 + o + 1);
+        } else {
+          Minv[(o + i) * m + o + k] = x;
+        }
       }
       __syncthreads();
-      // ↑↓ with T_1 .. T_(r-1), r the number of trailing one bits of stepid
+      // ↑↓ with T_1 .. T_(r-1), r the number of trailing one bits of stepid:
+      // X12 = R S_A^-1, X21 = L S_D^-1, the sum over the other half
       const int ones = __builtin_ctz(~step);
       for (int l = 1; l < ones; ++l) {
-        for (int idx = tid; idx < m * m; idx += NT) {
-          const int r = idx / m, c = idx - (idx / m) * m;
-          const int br = rb[r], bc = rb[c];
-          if ((br >> l) != (bc >> l)) continue;
-          const int hr = (br >> (l - 1)) & 1, hc = (bc >> (l - 1)) & 1;
-          if (hr == hc) continue;
-          const int v = br >> l;
-          // X12 = R S_A^-1 (k over D), X21 = L S_D^-1 (k over A)
-          const int k0 = hr == 0 ? bs[(v << l) + (1 << (l - 1))] : bs[v << l];
-          const int k1 = hr == 0 ? bs[(v + 1) << l] : bs[(v << l) + (1 << (l - 1))];
-          const Sq qt = square(l, r);
-          const double* tr = qt.base + (int64_t)r * qt.ld;
-          double acc = 0.0;
-          for (int k = k0; k < k1; ++k) acc = fma(tr[k], Minv[k * MMAX + c], acc);
-          Minv[r * MMAX + c] = acc;
+        if (row) {
+          const Unit u = unit(l);
+          const int c0 = u.inA ? u.uh : u.u0, c1 = u.inA ? u.u1 : u.uh;
+          const double* tr = u.sq + (int64_t)r * u.s;
+          for (int c = c0 + g; c < c1; c += G) {
+            double acc = 0.0;
+            for (int k = c0; k < c1; ++k) acc = fma(tr[k], Minv[k * m + c], acc);
+            Minv[r * m + c] = acc;
+          }
         }
         __syncthreads();
       }
     }
   }
-  for (int idx = tid; idx < m * m; idx += NT) {
-    const int r = idx / m, c = idx - (idx / m) * m;
-    X[mt.off + idx] = Minv[r * MMAX + c];
-  }
+  for (int idx = tid; idx < m * m; idx += NT) X[mt.off + idx] = Minv[idx];
   if (tid == 0) info[mt.id] = sing == 0x7fffffff ? 0 : (sing & 65535);
 }
 
-int level_tier_limit(int t) { return 8 << t; }
+namespace {
 
-size_t level_tier_tmax(int t) {
-  const size_t mm = (size_t)level_tier_limit(t) * level_tier_limit(t);
-  return mm * 5 / 2;
+// Launch classes: orders <= kLimit[c] on kThreads[c] threads.  The classes
+// above 32 split orders 33..64 where their LDS (m^2 + |T|, about 2.9 m^2
+// doubles with Table 2's partitions) lets 4, 3, 2 and 1 workgroups share a CU.
+constexpr int kLimit[kLevelClasses] = {8, 16, 32, 40, 48, 59, 64};
+
+template <int MMAX, int NT, int WPE>
+hipError_t launch_one(dim3 grid, size_t lds, hipStream_t s, const double* A, double* X, const SmallMat* mats,
+                      const int32_t* order, const int32_t* bounds, int32_t* info) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_level_scheme<MMAX, NT, WPE>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)(kLevelLdsDoubles * sizeof(double)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_level_scheme<MMAX, NT, WPE>), grid, dim3(NT), lds, s, A, X, mats, order, bounds, info);
+  return hipSuccess;
 }
 
-size_t level_tier_lds(int t) { return sizeof(double) * ((size_t)level_tier_limit(t) * level_tier_limit(t) + level_tier_tmax(t)); }
+}  // namespace
 
-hipError_t launch_level_tier(int tier, const double* A, double* X, const SmallMat* mats, const int32_t* order,
-                             int64_t count, const int32_t* bounds, int32_t* info, hipStream_t s) {
+int level_class_limit(int c) { return kLimit[c]; }
+
+hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat* mats, const int32_t* order,
+                              int64_t count, size_t lds_doubles, const int32_t* bounds, int32_t* info,
+                              hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const size_t lds = level_tier_lds(tier);
+  if (lds_doubles > kLevelLdsDoubles) return hipErrorInvalidValue;
+  const size_t lds = lds_doubles * sizeof(double);
   const dim3 grid((unsigned)count);
-  switch (tier) {
-    case 0: hipLaunchKernelGGL((k_level_scheme<8, 64>), grid, dim3(64), lds, s, A, X, mats, order, bounds, info); break;
-    case 1: hipLaunchKernelGGL((k_level_scheme<16, 64>), grid, dim3(64), lds, s, A, X, mats, order, bounds, info); break;
-    case 2: hipLaunchKernelGGL((k_level_scheme<32, 128>), grid, dim3(128), lds, s, A, X, mats, order, bounds, info); break;
-    case 3: {
-      // more than 64 KB of dynamic LDS: raise the kernel's limit once
-      static const hipError_t attr = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&k_level_scheme<64, 256>), hipFuncAttributeMaxDynamicSharedMemorySize,
-          (int)level_tier_lds(3));
-      if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL((k_level_scheme<64, 256>), grid, dim3(256), lds, s, A, X, mats, order, bounds, info);
-      break;
-    }
+  hipError_t e;
+  switch (c) {
+    case 0: e = launch_one<8, 64, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 1: e = launch_one<16, 128, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 2: e = launch_one<32, 256, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 3: e = launch_one<64, 512, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 4: e = launch_one<64, 512, 6>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 5: e = launch_one<64, 1024, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 6: e = launch_one<64, 1024, 4>(grid, lds, s, A, X, mats, order, bounds, info); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
