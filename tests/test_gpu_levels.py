@@ -70,7 +70,12 @@ def test_hadamard_and_kronecker_are_exact(gpu):
 
 
 def test_explicit_partitions_and_in_place(gpu):
-    parts = [[1, 1], [4, 4, 4, 4], [1, 2, 3, 4], [4], [1], [2, 2, 1, 3, 4, 4, 1, 2], [3] * 16, [4] * 16, [2] * 32]
+    # [1] * 32 and [1] * 64: as many blocks as rows (the closed-form leaves
+    # take more slots than the launch has threads at order 32); [4] * 10 +
+    # [2] * 6 (order 52) and [3] * 8 + [2] * 8 (order 40) sit in the middle
+    # and at the top of their launch classes
+    parts = [[1, 1], [4, 4, 4, 4], [1, 2, 3, 4], [4], [1], [2, 2, 1, 3, 4, 4, 1, 2], [3] * 16, [4] * 16, [2] * 32,
+             [1] * 32, [1] * 64, [4] * 10 + [2] * 6, [3] * 8 + [2] * 8]
     mats = [wl.spd_gram(sum(p), wl.stream_seed(4, 4000 + i)) for i, p in enumerate(parts)]
     for inplace in (False, True):
         X, info, _ = run_levels(mats, parts=parts, inplace=inplace)
