@@ -655,7 +655,7 @@ def bench_levels(args):
         "solves_per_s": round(plan.count / (ms_step * 1e-3), 1),
         "blockwise_sweep_ms_per_batch": round(ms_sweep, 4),
         "speedup_vs_blockwise_sweep": round(ms_sweep / ms_step, 3),
-        "roofline": {"bound": "alu", "kernel": "k_level_scheme (one workgroup per matrix, all seven order classes)",
+        "roofline": {"bound": "alu", "kernel": "k_level_scheme (one workgroup per matrix, one launch per order class)",
                      "achieved": round(d_fl / max(d_cnt, 1) / (avg_ms * 1e-3) / 1e12, 4) if d_ms > 0 else 0.0,
                      "peak": PEAK_FP64, "unit": "TFLOP/s",
                      "frac": round(d_fl / max(d_cnt, 1) / (avg_ms * 1e-3) / 1e12 / PEAK_FP64, 5) if d_ms > 0 else 0.0,

@@ -356,15 +356,17 @@ binv_status binv_invert_batched(binv_batch* plan, const double* A, double* X, in
  * met must be invertible (SPD inputs guarantee it).  It costs
  * n^3 (3 - 1/N_k) flops for uniform blocks against the sweep's 2 n^3.  One
  * workgroup per matrix with M_inv and the provisional sets on chip; orders
- * are launched in classes (<= 8, 16, 32, 40, 48, 59, 64), one launch each.
+ * are launched in classes (<= 8, 16, 32, 45, 52, 64), one launch each.
  * A, X, d_info and in-place use as for binv_invert_batched; d_info[i] is the
  * 1-based first row of the first block (earliest step, then lowest block)
  * whose determinant was exactly zero.  flags: BINV_F_SYNC (BINV_F_GRAPH is
  * accepted and has no effect: the call is one launch per order class).
  * Errors: BINV_E_INVALID for an order > 64, a block count that is not a
- * power of two, a block order > 4, or m^2 plus the provisional sets above
- * 19968 doubles (156 KB of LDS; no such partition of an order <= 64 reaches
- * it); checked on the first call, naming the matrix. */
+ * power of two, a block order > 4, or the inverse's on-chip part (m^2, or
+ * a^2 + d^2 for orders above 32 with a, d the orders of the top level's
+ * halves) plus the provisional sets above 19968 doubles (156 KB of LDS; no
+ * such partition of an order <= 64 reaches it); checked on the first call,
+ * naming the matrix. */
 binv_status binv_invert_batched_levels(binv_batch* plan, const double* A, double* X, int32_t* d_info,
                                        uint32_t flags, void* stream);
 

@@ -442,8 +442,10 @@ binv_status binv_invert_batched_levels(binv_batch* b, const double* A, double* X
           return bfail(BINV_E_INVALID, "the level scheme's diagonal blocks have orders <= 4" + at);
       int c = 0;
       while (mi > binv::level_class_limit(c)) ++c;
-      // M_inv and the provisional sets: every level-l unit's square
-      size_t need = (size_t)mi * mi;
+      // M_inv (its top-level diagonal squares where the class splits it)
+      // and the provisional sets (every level-l unit's square)
+      const int ha = (binv::level_class_split(c) && nk >= 2) ? b->bounds_host[bi + nk / 2] - b->bounds_host[bi] : mi;
+      size_t need = (size_t)ha * ha + (size_t)(mi - ha) * (mi - ha);
       double fl = 0.0;
       for (int j = 0; j < nk; ++j) {
         const double bj = b->bounds_host[bi + j + 1] - b->bounds_host[bi + j];
@@ -461,7 +463,7 @@ binv_status binv_invert_batched_levels(binv_batch* b, const double* A, double* X
           fl += 6.0 * na * nd * (na + nd) * (double)(nk >> l);
         }
       if (need > binv::kLevelLdsDoubles)
-        return bfail(BINV_E_INVALID, "the inverse and provisional sets exceed the on-chip store" + at);
+        return bfail(BINV_E_INVALID, "the inverse's diagonal squares and provisional sets exceed the on-chip store" + at);
       classes[c].push_back((int32_t)i);
       b->lvl_flops[c] += fl;
       b->lvl_lds[c] = std::max(b->lvl_lds[c], need);

@@ -207,12 +207,15 @@ hipError_t launch_small_refine(const double* A, double* X, const SmallMat* mats,
 
 // levels.hip: the paper's parallel algorithm (§5) on packed small matrices,
 // one workgroup per matrix.  Class c takes orders <= level_class_limit(c)
-// (8, 16, 32, 40, 48, 59, 64); a launch's dynamic LDS is lds_doubles (the
-// largest m^2 plus provisional sets of its matrices), at most
+// (8, 16, 32, 45, 52, 64); a launch's dynamic LDS is lds_doubles (the
+// largest a^2 + d^2 (the top-level halves' orders; m^2 where the class does
+// not split) plus provisional sets of its matrices), at most
 // kLevelLdsDoubles.
-constexpr int kLevelClasses = 7;
+constexpr int kLevelClasses = 6;
 constexpr size_t kLevelLdsDoubles = 19968;  // 156 KB of the CU's 160
 int level_class_limit(int c);
+// whether class c keeps only M_inv's top-level diagonal squares in LDS
+bool level_class_split(int c);
 hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                               int64_t count, size_t lds_doubles, const int32_t* bounds, int32_t* info,
                               hipStream_t s);

@@ -28,9 +28,13 @@
 // product phase a row's outputs form one contiguous column range (the other
 // half, or its own half, of the row's unit at the phase's level), so a group
 // walks only the outputs that exist.  The closed-form inverses take one
-// thread per block element.  A launch's LDS is the largest
-// m^2 + |T_1..T_K| of its matrices, and orders are launched in classes whose
-// LDS lets 4, 3, 2 or 1 workgroups share a CU.
+// thread per block element.  M_inv's two off-diagonal blocks of the top
+// level are written once, by the last step's ↑↓, and never read, so they go
+// straight to the output and LDS holds only its two top-level diagonal
+// squares (in the classes above order 32, where LDS bounds the occupancy).
+// A launch's LDS is the largest a^2 + d^2 + |T_1..T_K| of its matrices (a,
+// d the top-level halves' orders; m^2 + |T| without the split), and orders
+// are launched in classes whose LDS lets 4, 3 or 2 workgroups share a CU.
 #include <hip/hip_runtime.h>
 
 #include "binv_internal.h"
@@ -98,10 +102,11 @@ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
 // MMAX: largest order of the launch's matrices; NT threads; at least WPE
 // waves per SIMD (bounds the registers so that the class's workgroups fit a
-// CU together).  Dynamic LDS:
-// M_inv (m^2 doubles, row stride m) then the compact provisional sets (sized
-// on the host from the launch's partitions).
-template <int MMAX, int NT, int WPE>
+// CU together); SPLIT: M_inv's top-level off-diagonal blocks go straight to
+// the output.  Dynamic LDS: M_inv's top-level diagonal squares (a^2 then d^2
+// doubles; the whole m^2 without SPLIT) and the compact provisional sets
+// (sized on the host from the launch's partitions).
+template <int MMAX, int NT, int WPE, bool SPLIT>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) k_level_scheme(const double* __restrict__ A, double* __restrict__ X,
                                                      const SmallMat* __restrict__ mats,
                                                      const int32_t* __restrict__ order,
@@ -117,8 +122,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
   const SmallMat mt = mats[order[blockIdx.x]];
   const int m = mt.m, nk = mt.nb;
   const double* __restrict__ M = A + mt.off;
-  double* Minv = lds;
-  double* T = lds + m * m;
+  double* __restrict__ Xm = X + mt.off;
   const int tid = threadIdx.x;
   for (int j = tid; j <= nk; j += NT) bs[j] = bounds[mt.bnd + j];
   if (tid == 0) sing = 0x7fffffff;
@@ -140,6 +144,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
   const int G = NT / m;
   const int r = tid / G, g = tid - r * G;
   const bool row = r < m;
+
+  // M_inv: the top level's halves [0, ha) and [ha, m) (one square if N_k =
+  // 1 or without SPLIT); for x in one half, minv(x)[y] is element (x, y)
+  // with y in that half.  K: the level whose ↑↓ goes to the output (none
+  // without SPLIT).
+  const int K = SPLIT ? 31 - __builtin_clz(nk) : -1;
+  const int ha = (SPLIT && nk >= 2) ? bs[nk >> 1] : m, hd = m - ha;
+  double* MinvA = lds;
+  double* MinvD = lds + ha * ha;
+  double* T = MinvD + hd * hd;
+  auto minv = [&](int x) -> double* { return x < ha ? MinvA + x * ha : MinvD + (x - ha) * hd - ha; };
 
   // The square holding the level-l unit of row (or column) x: element (i, j)
   // of the unit is at base[i * ld + j] for the unit's rows and columns i, j
@@ -189,7 +204,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
         const int k0 = u.inA ? u.u0 : u.uh, k1 = u.inA ? u.uh : u.u1;
         // B and C lie in the row's level-src unit (src > l), or the input
         const Sq q = square(src, r);
-        const double* mi = Minv + r * m;
+        const double* mi = minv(r);
         double* out = u.sq + (int64_t)r * u.s;
         for (int c = c0 + g; c < c1; c += G) {
           const double* sc = q.base + c;
@@ -232,53 +247,64 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) 
         if (d == 0.0) {
           if (i == 0 && k == 0) atomicMin(&sing, step * 65536 + o + 1);
         } else {
-          Minv[(o + i) * m + o + k] = x;
+          minv(o + i)[o + k] = x;
         }
       }
       __syncthreads();
       // ↑↓ with T_1 .. T_(r-1), r the number of trailing one bits of stepid:
-      // X12 = R S_A^-1, X21 = L S_D^-1, the sum over the other half
+      // X12 = R S_A^-1, X21 = L S_D^-1, the sum over the other half; the top
+      // level's (last step only) goes to the output
       const int ones = __builtin_ctz(~step);
       for (int l = 1; l < ones; ++l) {
         if (row) {
           const Unit u = unit(l);
           const int c0 = u.inA ? u.uh : u.u0, c1 = u.inA ? u.u1 : u.uh;
           const double* tr = u.sq + (int64_t)r * u.s;
+          double* dst = l == K ? Xm + (int64_t)r * m : minv(r);
           for (int c = c0 + g; c < c1; c += G) {
             double acc = 0.0;
-            for (int k = c0; k < c1; ++k) acc = fma(tr[k], Minv[k * m + c], acc);
-            Minv[r * m + c] = acc;
+            for (int k = c0; k < c1; ++k) acc = fma(tr[k], minv(k)[c], acc);
+            dst[c] = acc;
           }
         }
-        __syncthreads();
+        // nothing reads the top level's blocks: no barrier (and no wait for
+        // their stores) after them
+        if (l != K) __syncthreads();
       }
     }
   }
-  for (int idx = tid; idx < m * m; idx += NT) X[mt.off + idx] = Minv[idx];
+  // the top-level diagonal squares (the off-diagonal blocks are written)
+  if (row) {
+    const int c0 = r < ha ? 0 : ha, c1 = r < ha ? ha : m;
+    const double* src_row = minv(r);
+    for (int c = c0 + g; c < c1; c += G) Xm[(int64_t)r * m + c] = src_row[c];
+  }
   if (tid == 0) info[mt.id] = sing == 0x7fffffff ? 0 : (sing & 65535);
 }
 
 namespace {
 
-// Launch classes: orders <= kLimit[c] on kThreads[c] threads.  The classes
-// above 32 split orders 33..64 where their LDS (m^2 + |T|, about 2.9 m^2
-// doubles with Table 2's partitions) lets 4, 3, 2 and 1 workgroups share a CU.
-constexpr int kLimit[kLevelClasses] = {8, 16, 32, 40, 48, 59, 64};
+// Launch classes: orders <= kLimit[c].  The classes above 32 split orders
+// 33..64 where their LDS (a^2 + d^2 + |T|, about 2.4 m^2 doubles with Table
+// 2's partitions) lets 4, 3 and 2 workgroups share a CU.
+constexpr int kLimit[kLevelClasses] = {8, 16, 32, 45, 52, 64};
 
-template <int MMAX, int NT, int WPE>
+template <int MMAX, int NT, int WPE, bool SPLIT>
 hipError_t launch_one(dim3 grid, size_t lds, hipStream_t s, const double* A, double* X, const SmallMat* mats,
                       const int32_t* order, const int32_t* bounds, int32_t* info) {
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_level_scheme<MMAX, NT, WPE>),
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_level_scheme<MMAX, NT, WPE, SPLIT>),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)(kLevelLdsDoubles * sizeof(double)));
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_level_scheme<MMAX, NT, WPE>), grid, dim3(NT), lds, s, A, X, mats, order, bounds, info);
+  hipLaunchKernelGGL((k_level_scheme<MMAX, NT, WPE, SPLIT>), grid, dim3(NT), lds, s, A, X, mats, order, bounds, info);
   return hipSuccess;
 }
 
 }  // namespace
 
 int level_class_limit(int c) { return kLimit[c]; }
+
+bool level_class_split(int c) { return kLimit[c] > 32; }
 
 hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat* mats, const int32_t* order,
                               int64_t count, size_t lds_doubles, const int32_t* bounds, int32_t* info,
@@ -289,13 +315,12 @@ hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat*
   const dim3 grid((unsigned)count);
   hipError_t e;
   switch (c) {
-    case 0: e = launch_one<8, 64, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 1: e = launch_one<16, 128, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 2: e = launch_one<32, 256, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 3: e = launch_one<64, 512, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 4: e = launch_one<64, 512, 6>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 5: e = launch_one<64, 1024, 8>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 6: e = launch_one<64, 1024, 4>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 0: e = launch_one<8, 64, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 1: e = launch_one<16, 128, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 2: e = launch_one<32, 256, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 3: e = launch_one<64, 512, 8, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 4: e = launch_one<64, 512, 6, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 5: e = launch_one<64, 1024, 8, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
