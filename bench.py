@@ -22,6 +22,9 @@
   eager and replayed from a HIP graph.
 --workload host: out of core, n = 16384 in pinned host memory with a device
   budget of a quarter of the matrix; bitwise equal to the in-core result.
+--workload mfma: the sustained rates of the FP64 instructions the trailing
+  update can be built on (the 4x4x4 and 16x16x4 MFMAs and the vector FMA),
+  from the standalone program paper_2305_11103_amd/mfma_rate.
 
 Throughput counts 2 n^3 flops per inverse and is only reported as valid when
 the oracle's compensated residual rho = ||AX - I||_F / sqrt(n) (sampled rows,
@@ -1018,12 +1021,51 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mfma(args):
+    """The FP64 instruction rates behind the GEMM core's design: runs the
+    standalone measurement program (a child process; this process touches no
+    GPU) and reports the 4x4x4 MFMA's sustained rate as the line's value."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2305_11103_amd", "mfma_rate")
+    if not os.path.exists(exe):
+        raise SystemExit("paper_2305_11103_amd/mfma_rate is not built (run __graft_entry__.build())")
+    reps = max(args.steps, 1)
+    log(f"bench: running {exe} ({reps} timed launches per instruction)")
+    r = subprocess.run([exe, str(reps)], capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        raise SystemExit(f"mfma_rate failed ({r.returncode}): {r.stderr.strip()}")
+    lines = [json.loads(x) for x in r.stdout.splitlines() if x.strip().startswith("{")]
+    dev = lines[0]
+    rates = {x["instruction"]: x for x in lines[1:]}
+    for x in lines[1:]:
+        log(f"bench: {x['instruction']}: {x['tflops_best']:.2f} TFLOP/s best, {x['tflops_median']:.2f} median "
+            f"({x['waves_per_simd']} waves per SIMD)")
+    m4 = rates["v_mfma_f64_4x4x4_4b_f64"]
+    out = {
+        "metric": "sustained FP64 TFLOP/s of v_mfma_f64_4x4x4_4b_f64 (independent chains, every CU)",
+        "value": round(m4["tflops_median"], 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(m4["ms_median"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "FP64 instruction-rate microbenchmark: 4x4x4 and 16x16x4 MFMA, vector FMA, "
+                               f"{dev['accumulators_per_wave']} independent chains per wave",
+                   "compute_units": dev["compute_units"], "device": dev["device"]},
+        "rates": {k: {"tflops_best": v["tflops_best"], "tflops_median": v["tflops_median"],
+                      "waves_per_simd": v["waves_per_simd"], "flops_per_wave_instruction":
+                      v["flops_per_wave_instruction"]} for k, v in rates.items()},
+        "roofline": {"bound": "mfma", "kernel": "k_rate_mfma4 (v_mfma_f64_4x4x4_4b_f64 chains)",
+                     "achieved": round(m4["tflops_median"], 3), "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": round(m4["tflops_median"] / PEAK_FP64, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve", "levels", "small", "host"],
+    ap.add_argument("--workload", choices=["plain", "batched", "mixed", "serve", "levels", "small", "host", "mfma"],
                     default="plain")
     ap.add_argument("--gen", choices=["device", "host"], default="device",
                     help="where the plain workload's Haar factor is formed")
@@ -1043,7 +1085,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     {"plain": bench_plain, "batched": bench_batched, "mixed": bench_mixed, "serve": bench_serve,
-     "levels": bench_levels, "small": bench_small, "host": bench_host}[args.workload](args)
+     "levels": bench_levels, "small": bench_small, "host": bench_host, "mfma": bench_mfma}[args.workload](args)
 
 
 if __name__ == "__main__":
