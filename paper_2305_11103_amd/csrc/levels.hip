@@ -286,7 +286,10 @@ namespace {
 
 // Launch classes: orders <= kLimit[c].  The classes above 32 split orders
 // 33..64 where their LDS (a^2 + d^2 + |T|, about 2.4 m^2 doubles with Table
-// 2's partitions) lets 4, 3 and 2 workgroups share a CU.
+// 2's partitions) lets 4, 3 and 2 workgroups share a CU.  Threads and the
+// register bound per class are the measured best (a bound that makes the
+// kernel spill cost more than the occupancy it buys at orders <= 8 and
+// 53..64).
 constexpr int kLimit[kLevelClasses] = {8, 16, 32, 45, 52, 64};
 
 template <int MMAX, int NT, int WPE, bool SPLIT>
@@ -315,12 +318,12 @@ hipError_t launch_level_class(int c, const double* A, double* X, const SmallMat*
   const dim3 grid((unsigned)count);
   hipError_t e;
   switch (c) {
-    case 0: e = launch_one<8, 64, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 0: e = launch_one<8, 64, 4, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
     case 1: e = launch_one<16, 128, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
     case 2: e = launch_one<32, 256, 8, false>(grid, lds, s, A, X, mats, order, bounds, info); break;
     case 3: e = launch_one<64, 512, 8, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
     case 4: e = launch_one<64, 512, 6, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
-    case 5: e = launch_one<64, 1024, 8, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
+    case 5: e = launch_one<64, 512, 4, true>(grid, lds, s, A, X, mats, order, bounds, info); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
