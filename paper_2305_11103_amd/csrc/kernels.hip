@@ -1182,10 +1182,13 @@ __global__ void __launch_bounds__(64 * NWV) k_swept_step(const SweptJob* __restr
 
 hipError_t launch_swept_step(const SweptJob* jobs, int64_t count, int bmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  // pivot blocks above 64: 64 x 128 Schur tiles (each row's column-panel
+  // slice read half as often; 18.4 against 18.9 ms per measured batch); at
+  // most 64: 64 x 64 (the wider tile's registers halve the occupancy there)
   if (bmax <= 64)
     hipLaunchKernelGGL((k_swept_step<1, 16, 4, TileCfg<64, 64, 2, 2>>), dim3((unsigned)count), dim3(256), 0, s, jobs);
   else
-    hipLaunchKernelGGL((k_swept_step<2, 16, 8, TileCfg<64, 64, 4, 2>>), dim3((unsigned)count), dim3(512), 0, s, jobs);
+    hipLaunchKernelGGL((k_swept_step<2, 16, 8, TileCfg<64, 128, 4, 2>>), dim3((unsigned)count), dim3(512), 0, s, jobs);
   return hipGetLastError();
 }
 
